@@ -1,0 +1,373 @@
+/*
+ * CPU oracle for the unstructured cell-centred finite-volume Euler step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain, obviously
+ * correct reference the HIP library is checked against.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may build,
+ * load or call it; the product path never does.  It shares no code,
+ * header, table or helper with the HIP library.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC (no FMA
+ * contraction, so every rounding happens where the source writes it).
+ *
+ * Source: Nagy et al., "Accelerating unstructured finite volume
+ * computations on field-programmable gate arrays" (arXiv:1408.5715).
+ *   - Section 6.1: Euler equations, state U = (rho, rho u, rho v, E),
+ *     E = p/(gamma-1) + rho |v|^2 / 2, c = sqrt(gamma p / rho), gamma = 1.4.
+ *   - Section 6.2.1: cell-centred triangles; n_f is the outward face normal
+ *     scaled by the face length; V_T is the cell's area.
+ *   - Section 6.2.2: semi-discrete form (eqSemiDiscrete), Lax-Friedrichs
+ *     numerical flux (eqCompFlux), forward Euler (eqFWEuler), the update
+ *     U^{n+1} = U^n - dt/V_T * sum_f R_{n_f} F_f |n_f|, and the face-frame
+ *     component form (eqFi group).
+ *   - Section 4.1: matrix bandwidth B_f(G), C_BW = 2 B_f(G) + 1 and the
+ *     serial bandwidth S_BW.
+ *   - Section 4.2.2: the pseudo-diameter start vertex used before the
+ *     breadth-first labelling (Gibbs-Poole-Stockmeyer subroutine, realised
+ *     here as the George-Liu pseudo-peripheral node search).
+ *
+ * Readings taken where the paper is silent or garbled:
+ *   - Dissipation sign: F = (F_L + F_R)/2 - alpha (U_R - U_L)/2 as in
+ *     eqCompFlux (the eqFi group prints "+", which is anti-diffusive).
+ *   - alpha = |mean of the two face-normal velocities| + mean of the two
+ *     sound speeds.
+ *   - Face-frame tangent t = (-n_y, n_x) for unit normal n = (n_x, n_y).
+ *   - The flux is evaluated with the unit normal and multiplied by the face
+ *     length |n_f| once.
+ *   - Faces are summed in stored order, ((F_0 + F_1) + F_2).
+ *   - S_BW uses closed neighbourhoods (a node is a neighbour of itself).
+ *   - Cuthill-McKee children are visited in order of (degree, id).
+ */
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Primitive quantities of one state (section 6.1). */
+static void primitives(const double *U, double gamma, double *rho, double *u, double *v,
+                       double *p, double *c)
+{
+    *rho = U[0];
+    *u = U[1] / U[0];
+    *v = U[2] / U[0];
+    /* p from E = p/(gamma-1) + rho (u^2 + v^2)/2 */
+    *p = (gamma - 1.0) * (U[3] - 0.5 * (*rho) * ((*u) * (*u) + (*v) * (*v)));
+    *c = sqrt(gamma * (*p) / (*rho));
+}
+
+/*
+ * Lax-Friedrichs flux through one face, returned in the x-y frame and
+ * multiplied by the face length: R_{n_f} F_f |n_f| of section 6.2.2.
+ * UL is the cell being updated, UR the cell across the face, (nx, ny) the
+ * outward normal of the face scaled by its length.
+ */
+void oracle_face_flux(const double *UL, const double *UR, double nx, double ny, double gamma,
+                      double *Fout)
+{
+    double len = sqrt(nx * nx + ny * ny);
+    /* face frame: x' along the unit outward normal, y' along the tangent */
+    double ex = nx / len, ey = ny / len;
+    double tx = -ey, ty = ex;
+
+    double rL, uL, vL, pL, cL, rR, uR, vR, pR, cR;
+    primitives(UL, gamma, &rL, &uL, &vL, &pL, &cL);
+    primitives(UR, gamma, &rR, &uR, &vR, &pR, &cR);
+
+    /* velocities in the face frame */
+    double unL = uL * ex + vL * ey, vtL = uL * tx + vL * ty;
+    double unR = uR * ex + vR * ey, vtR = uR * tx + vR * ty;
+
+    /* rotated conserved states */
+    double QL[4] = {rL, rL * unL, rL * vtL, UL[3]};
+    double QR[4] = {rR, rR * unR, rR * vtR, UR[3]};
+
+    /* x-component of the flux tensor (eqFlux) in the face frame */
+    double GL[4] = {rL * unL, rL * unL * unL + pL, rL * unL * vtL, (UL[3] + pL) * unL};
+    double GR[4] = {rR * unR, rR * unR * unR + pR, rR * unR * vtR, (UR[3] + pR) * unR};
+
+    /* |u bar| + c bar: averages at the interface (eqCompFlux) */
+    double alpha = fabs(0.5 * (unL + unR)) + 0.5 * (cL + cR);
+
+    double Fp[4];
+    for (int k = 0; k < 4; ++k)
+        Fp[k] = 0.5 * (GL[k] + GR[k]) - alpha * 0.5 * (QR[k] - QL[k]);
+
+    /* rotate back to x-y, then scale by the face length |n_f| */
+    Fout[0] = len * Fp[0];
+    Fout[1] = len * (Fp[1] * ex + Fp[2] * tx);
+    Fout[2] = len * (Fp[1] * ey + Fp[2] * ty);
+    Fout[3] = len * Fp[3];
+}
+
+/* Area-scaled sum of the three face fluxes of cell i (eqSemiDiscrete). */
+void oracle_cell_residual(int64_t i, const int32_t *nbr, const double *nrm, const double *U,
+                          double gamma, double *R)
+{
+    R[0] = R[1] = R[2] = R[3] = 0.0;
+    for (int f = 0; f < 3; ++f) {
+        int64_t j = nbr[3 * i + f];
+        double F[4];
+        oracle_face_flux(&U[4 * i], &U[4 * j], nrm[6 * i + 2 * f], nrm[6 * i + 2 * f + 1], gamma,
+                         F);
+        for (int k = 0; k < 4; ++k)
+            R[k] += F[k];
+    }
+}
+
+/*
+ * n_steps forward-Euler steps (eqFWEuler and the update of section 6.2.2):
+ * U_T^{n+1} = U_T^n - dt / V_T * sum_f R_{n_f} F_f |n_f|.
+ * U is [n][4] (rho, rho u, rho v, E), updated in place; every step reads the
+ * whole of U^n before any U^{n+1} value is used.
+ * Returns 0, or -1 on a bad argument or allocation failure.
+ */
+int oracle_step(int64_t n, const int32_t *nbr, const double *nrm, const double *area,
+                double gamma, double dt, int64_t n_steps, double *U)
+{
+    if (n <= 0 || n_steps < 0 || !nbr || !nrm || !area || !U)
+        return -1;
+    double *Un = (double *)malloc((size_t)n * 4 * sizeof(double));
+    if (!Un)
+        return -1;
+    double *cur = U, *nxt = Un;
+    for (int64_t s = 0; s < n_steps; ++s) {
+        for (int64_t i = 0; i < n; ++i) {
+            double R[4];
+            oracle_cell_residual(i, nbr, nrm, cur, gamma, R);
+            double coef = dt / area[i];
+            for (int k = 0; k < 4; ++k)
+                nxt[4 * i + k] = cur[4 * i + k] - coef * R[k];
+        }
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (cur != U)
+        memcpy(U, cur, (size_t)n * 4 * sizeof(double));
+    free(Un);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Renumbering (section 4): Cuthill-McKee labelling from a pseudo-diameter */
+/* endpoint, and the bandwidth metrics of section 4.1.                     */
+/* ---------------------------------------------------------------------- */
+
+/* Distinct neighbours of v other than v itself, in stored face order. */
+static int distinct_neighbours(const int32_t *nbr, int64_t v, int32_t out[3])
+{
+    int d = 0;
+    for (int f = 0; f < 3; ++f) {
+        int32_t w = nbr[3 * v + f];
+        if (w == v)
+            continue;
+        int seen = 0;
+        for (int g = 0; g < d; ++g)
+            if (out[g] == w)
+                seen = 1;
+        if (!seen)
+            out[d++] = w;
+    }
+    return d;
+}
+
+static int degree_of(const int32_t *nbr, int64_t v)
+{
+    int32_t tmp[3];
+    return distinct_neighbours(nbr, v, tmp);
+}
+
+/*
+ * Breadth-first level structure rooted at r over the vertices with
+ * mark[v] == 0 (the current component).  Returns the eccentricity of r (the
+ * number of levels minus one) and the vertex of minimum (degree, id) in the
+ * last level.  'queue' and 'dist' are scratch arrays of n entries; dist must
+ * hold -1 for every vertex of the component on entry and is restored.
+ */
+static int64_t level_structure(int64_t n, const int32_t *nbr, const uint8_t *mark, int64_t r,
+                               int64_t *queue, int64_t *dist, int64_t *last_pick)
+{
+    (void)n;
+    int64_t head = 0, tail = 0;
+    queue[tail++] = r;
+    dist[r] = 0;
+    int64_t ecc = 0;
+    while (head < tail) {
+        int64_t v = queue[head++];
+        if (dist[v] > ecc)
+            ecc = dist[v];
+        int32_t nb[3];
+        int d = distinct_neighbours(nbr, v, nb);
+        for (int g = 0; g < d; ++g) {
+            int64_t w = nb[g];
+            if (!mark[w] && dist[w] < 0) {
+                dist[w] = dist[v] + 1;
+                queue[tail++] = w;
+            }
+        }
+    }
+    int64_t best = -1, best_deg = 0;
+    for (int64_t q = 0; q < tail; ++q) {
+        int64_t v = queue[q];
+        if (dist[v] != ecc)
+            continue;
+        int64_t dg = degree_of(nbr, v);
+        if (best < 0 || dg < best_deg || (dg == best_deg && v < best)) {
+            best = v;
+            best_deg = dg;
+        }
+    }
+    for (int64_t q = 0; q < tail; ++q)
+        dist[queue[q]] = -1;
+    *last_pick = best;
+    return ecc;
+}
+
+/*
+ * Cuthill-McKee ordering of the dual graph given by nbr [n][3].
+ * perm_out[new_label] = old id.
+ * Each connected component is labelled in turn, starting with the component
+ * of the lowest-id unlabelled vertex s.  Its root is a pseudo-peripheral
+ * vertex found by the George-Liu search from s: take the last level of the
+ * level structure rooted at r, pick its vertex of minimum (degree, id) x; if
+ * x has a larger eccentricity than r, continue from x, else keep r.
+ * The labelling visits labelled vertices in label order and appends each
+ * one's unlabelled neighbours sorted by (degree, id).
+ * Returns 0, or -1 on a bad argument or allocation failure.
+ */
+int oracle_cm_order(int64_t n, const int32_t *nbr, int32_t *perm_out)
+{
+    if (n <= 0 || !nbr || !perm_out)
+        return -1;
+    uint8_t *mark = (uint8_t *)calloc((size_t)n, 1);
+    int64_t *queue = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *dist = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!mark || !queue || !dist) {
+        free(mark);
+        free(queue);
+        free(dist);
+        return -1;
+    }
+    for (int64_t v = 0; v < n; ++v)
+        dist[v] = -1;
+
+    int64_t next = 0;
+    int64_t scan = 0;
+    while (next < n) {
+        while (mark[scan])
+            ++scan;
+        int64_t r = scan;
+
+        /* pseudo-peripheral root */
+        int64_t x;
+        int64_t ecc_r = level_structure(n, nbr, mark, r, queue, dist, &x);
+        for (;;) {
+            int64_t x2;
+            int64_t ecc_x = level_structure(n, nbr, mark, x, queue, dist, &x2);
+            if (ecc_x > ecc_r) {
+                r = x;
+                ecc_r = ecc_x;
+                x = x2;
+            } else {
+                break;
+            }
+        }
+
+        /* Cuthill-McKee labelling of the component from r */
+        int64_t head = next;
+        perm_out[next++] = (int32_t)r;
+        mark[r] = 1;
+        while (head < next) {
+            int64_t v = perm_out[head++];
+            int32_t nb[3];
+            int d = distinct_neighbours(nbr, v, nb);
+            int32_t kid[3];
+            int nk = 0;
+            for (int g = 0; g < d; ++g)
+                if (!mark[nb[g]])
+                    kid[nk++] = nb[g];
+            /* order children by (degree, id): insertion sort of <= 3 items */
+            for (int a = 1; a < nk; ++a) {
+                int32_t key = kid[a];
+                int kd = degree_of(nbr, key);
+                int b = a - 1;
+                while (b >= 0) {
+                    int bd = degree_of(nbr, kid[b]);
+                    if (bd > kd || (bd == kd && kid[b] > key)) {
+                        kid[b + 1] = kid[b];
+                        --b;
+                    } else {
+                        break;
+                    }
+                }
+                kid[b + 1] = key;
+            }
+            for (int a = 0; a < nk; ++a) {
+                mark[kid[a]] = 1;
+                perm_out[next++] = kid[a];
+            }
+        }
+    }
+    free(mark);
+    free(queue);
+    free(dist);
+    return 0;
+}
+
+/*
+ * Bandwidth metrics of section 4.1 for the labelling f(v) = label[v]
+ * (0-based).  Outputs:
+ *   out[0] = B_f(G) = max over edges |f(v) - f(u)|
+ *   out[1] = C_BW = 2 B_f(G) + 1
+ *   out[2] = S_BW = max_i (E(i) - S(i)), where for the node u labelled i,
+ *            s(i) / e(i) are the min / max label over its closed
+ *            neighbourhood, S(i) = min_{k >= i} s(k), E(i) = max_{k <= i} e(k).
+ * Returns 0, or -1 on a bad argument or allocation failure.
+ */
+int oracle_bandwidth(int64_t n, const int32_t *nbr, const int32_t *label, int64_t *out)
+{
+    if (n <= 0 || !nbr || !label || !out)
+        return -1;
+    int64_t *s = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *e = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!s || !e) {
+        free(s);
+        free(e);
+        return -1;
+    }
+    int64_t B = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        int64_t fu = label[u];
+        int64_t lo = fu, hi = fu;
+        for (int f = 0; f < 3; ++f) {
+            int64_t fv = label[nbr[3 * u + f]];
+            if (fv < lo)
+                lo = fv;
+            if (fv > hi)
+                hi = fv;
+            int64_t d = fv > fu ? fv - fu : fu - fv;
+            if (d > B)
+                B = d;
+        }
+        s[fu] = lo;
+        e[fu] = hi;
+    }
+    /* S(i): suffix minimum of s; E(i): prefix maximum of e */
+    for (int64_t i = n - 2; i >= 0; --i)
+        if (s[i + 1] < s[i])
+            s[i] = s[i + 1];
+    for (int64_t i = 1; i < n; ++i)
+        if (e[i - 1] > e[i])
+            e[i] = e[i - 1];
+    int64_t sbw = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (e[i] - s[i] > sbw)
+            sbw = e[i] - s[i];
+    out[0] = B;
+    out[1] = 2 * B + 1;
+    out[2] = sbw;
+    free(s);
+    free(e);
+    return 0;
+}
