@@ -50,7 +50,8 @@ def test_permutation_relabels_consistently():
 def test_initial_states():
     m = periodic_mesh(32)
     P = ic.vortex_primitive(m.centroid)
-    assert P.rho.min() > 0.78 and P.rho.max() <= 1.0
+    # T_min = 1 - 0.4 * 25 / (8 * 1.4 * pi^2) * e = 0.754, rho_min = T_min^2.5 = 0.494
+    assert 0.49 < P.rho.min() < 0.51 and P.rho.max() <= 1.0
     U = ic.to_conserved(P)
     assert U.shape == (m.n, 4)
     B = ic.bumps_primitive(m.centroid)
