@@ -1,0 +1,238 @@
+"""Throughput of the explicit unstructured FV Euler step on one MI355X.
+
+One bench "step" is one whole job of the hot path on the 1024 x 1024-quad
+periodic mesh (2,097,152 triangles) whose cells arrive in random order, with
+the mesh and the initial state already resident in device memory:
+
+  1. GPU Cuthill-McKee renumbering of the mesh (pseudo-peripheral search and
+     breadth-first labelling) and the permutation gather of every per-cell
+     array,
+  2. the initial state gathered into the new order,
+  3. 1000 forward-Euler Lax-Friedrichs steps (FP64),
+  4. the final state gathered back to the original order (in device memory).
+
+value = cells x 1000 / job time (cell updates per second, whole job).
+Also reported: the step kernel alone (HIP events over its 1000 launches on
+the library's stream) against the HBM roofline, the same kernel on the
+random (not renumbered) order, and the CPU oracle timed on a bounded sample
+of the same job.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--fv-steps 1000]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic HBM bytes of one cell update (each per-cell array touched
+# once; the three neighbour states are reuse the renumbering keeps on chip):
+# read U 32 + neighbour ids 12 + face normals 48 + 1/area 8, write U 32.
+BYTES_PER_CELL_UPDATE = 132
+HBM_PEAK_GBS = 8000.0
+STEP_SOURCE = os.path.join(ROOT, "paper_1408_5715_amd", "csrc", "fv_step.hip")
+
+# HBM traffic of one step launch on this workload, from rocprofv3 --pmc
+# FETCH_SIZE / WRITE_SIZE runs (profiles/fv_step_c2_counters.md), valid only
+# for the step kernel source with this SHA-256.
+MEASURED_TRAFFIC = None
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_sha() -> str:
+    with open(STEP_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def cpu_baseline(m, U0, dt, fv_steps: int, sample_steps: int) -> dict:
+    """The oracle as it stands, single-threaded: CM order of the random-order
+    mesh plus sample_steps steps on the renumbered mesh, scaled to the job."""
+    import numpy as np
+
+    import oracle
+    from fvgen.mesh import permute_mesh
+
+    t0 = time.perf_counter()
+    perm = oracle.cm_order(m.nbr)
+    t_cm = time.perf_counter() - t0
+    mc = permute_mesh(m, perm.astype(np.int64))
+    Uc = U0[perm]
+    t0 = time.perf_counter()
+    oracle.step(mc.nbr, mc.nrm, mc.area, Uc, dt, sample_steps)
+    t_step = (time.perf_counter() - t0) / sample_steps
+    job = t_cm + fv_steps * t_step
+    return {
+        "value": m.n * fv_steps / job,
+        "unit": "cell-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle Cuthill-McKee order of the {m.n}-cell mesh ({t_cm:.2f} s) plus "
+                   f"{sample_steps} oracle steps on the renumbered mesh ({t_step:.3f} s/step), "
+                   f"scaled to the {fv_steps}-step job"),
+        "step_only_value": m.n / t_step,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed jobs")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed jobs")
+    ap.add_argument("--fv-steps", type=int, default=1000, help="time steps per job")
+    ap.add_argument("--N", type=int, default=1024, help="quads per side")
+    ap.add_argument("--cpu-sample-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the step would shard by contiguous ranges of the renumbered order with a "
+              "halo exchange per step; that exchange is not implemented).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1408_5715_amd as fv
+    from fvgen import ic
+    from fvgen.mesh import periodic_mesh, permute_mesh, random_permutation
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    N = args.N
+    log(f"generating the {N}x{N}-quad mesh")
+    m = permute_mesh(periodic_mesh(N, seed=1), random_permutation(2 * N * N, 2))
+    P = ic.bumps_primitive(m.centroid, seed=3)
+    U0 = ic.to_conserved(P)
+    dt = ic.cfl_dt(P, m.area, m.perimeter, 0.4)
+    n = m.n
+
+    log("uploading")
+    s = fv.Solver(m.nbr, m.nrm, m.area, device=dev)
+    stream = s.stream
+    dU0 = torch.from_numpy(U0).to(dev)
+    dout = torch.empty_like(dU0)
+    torch.cuda.synchronize()
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def job(record=None):
+        e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+        e0.record(stream)
+        fv.fv_renumber(s.ctx, fv.FV_ORDER_CM)
+        fv.fv_upload_state_device(s.ctx, dU0)
+        e1.record(stream)
+        fv.fv_step(s.ctx, args.fv_steps, dt)
+        e2.record(stream)
+        fv.fv_download_state_device(s.ctx, dout)
+        e3.record(stream)
+        if record is not None:
+            record.append((e0, e1, e2, e3))
+
+    log(f"warmup: {args.warmup} job(s)")
+    for _ in range(args.warmup):
+        job()
+    torch.cuda.synchronize()
+
+    log(f"timing {args.steps} job(s) of {args.fv_steps} steps")
+    marks = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        job(marks)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    renum_ms = [a.elapsed_time(b) for a, b, _, _ in marks]
+    step_ms = [b.elapsed_time(c) for _, b, c, _ in marks]
+    down_ms = [c.elapsed_time(d) for _, _, c, d in marks]
+    ms_per_job = wall * 1e3 / args.steps
+    value = n * args.fv_steps * args.steps / wall
+    step_kernel_s = float(np.mean(step_ms)) * 1e-3 / args.fv_steps
+    achieved = BYTES_PER_CELL_UPDATE * n / step_kernel_s / 1e9
+
+    # the same kernel on the random (identity) order, for the locality effect
+    log("timing the step on the random order")
+    fv.fv_renumber(s.ctx, fv.FV_ORDER_IDENTITY)
+    fv.fv_upload_state_device(s.ctx, dU0)
+    fv.fv_step(s.ctx, 50, dt)
+    a, b = ev(), ev()
+    a.record(stream)
+    fv.fv_step(s.ctx, args.fv_steps, dt)
+    b.record(stream)
+    torch.cuda.synchronize()
+    random_step_s = a.elapsed_time(b) * 1e-3 / args.fv_steps
+    s.close()
+
+    traffic = None
+    if MEASURED_TRAFFIC is not None and MEASURED_TRAFFIC.get("source_sha") == source_sha() \
+            and MEASURED_TRAFFIC.get("cells") == n:
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle baseline ({args.cpu_sample_steps} steps + CM order)")
+        cpu = cpu_baseline(m, U0, dt, args.fv_steps, args.cpu_sample_steps)
+
+    rec = {
+        "metric": "cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_job,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"periodic jittered {N}x{N}-quad triangle mesh ({n} cells), random cell "
+                         f"order, Mach 0.5 stream + 32 bumps, CFL 0.4; job = GPU Cuthill-McKee "
+                         f"renumbering + gather + {args.fv_steps} FP64 Lax-Friedrichs steps + "
+                         f"gather back"),
+            "cells": n,
+            "fv_steps_per_job": args.fv_steps,
+            "dt": dt,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "fv_step_kernel",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "bytes_per_cell_update": BYTES_PER_CELL_UPDATE,
+            "avg_launch_us": step_kernel_s * 1e6,
+        },
+        "cpu_baseline": cpu,
+        "breakdown": {
+            "renumber_and_upload_ms": float(np.median(renum_ms)),
+            "steps_ms": float(np.median(step_ms)),
+            "download_ms": float(np.median(down_ms)),
+            "step_only_cell_updates_per_s": n / step_kernel_s,
+            "random_order_step_us": random_step_s * 1e6,
+            "random_order_cell_updates_per_s": n / random_step_s,
+        },
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

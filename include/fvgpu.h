@@ -1,0 +1,158 @@
+/*
+ * fvgpu.h -- C ABI of the MI355X (gfx950) finite-volume Euler library.
+ *
+ * The library advances the 2D Euler equations on a closed unstructured
+ * triangle mesh with the explicit cell-centred finite-volume scheme of
+ * Nagy et al., "Accelerating unstructured finite volume computations on
+ * field-programmable gate arrays" (arXiv:1408.5715), section 6:
+ *
+ *   U_T^{n+1} = U_T^n - dt / V_T * sum_{f=0..2} R_{n_f} F_f |n_f|
+ *
+ * with U = (rho, rho u, rho v, E), the Lax-Friedrichs numerical flux F_f
+ * (eqCompFlux) evaluated between the cell and its neighbour across face f,
+ * n_f the outward face normal scaled by the face length and V_T the cell
+ * area (section 6.2.1).  It also renumbers cells for locality (section 4:
+ * breadth-first Cuthill-McKee labelling from a pseudo-diameter endpoint) and
+ * applies the permutation on the device.
+ *
+ * Conventions for every entry point:
+ *   - All work runs on the HIP stream given to fv_create, in issue order.
+ *   - Host arrays are read or written during the call only; the caller owns
+ *     them.  Device memory is one arena the caller allocates and owns; the
+ *     library never allocates or frees device memory.
+ *   - A status < 0 is an error; fv_last_error() returns a message for the
+ *     calling thread.  Argument and mesh validation happens on the host
+ *     before any HIP call, so a rejected call leaves the device untouched.
+ *   - Results are deterministic: the step is gather-only (no atomics), so the
+ *     same inputs give bitwise-equal outputs, whatever the cell numbering.
+ *   - A context is not thread-safe; use one context per thread.
+ */
+#ifndef FVGPU_H
+#define FVGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fv_ctx fv_ctx;
+typedef int32_t fv_status;
+
+#define FV_OK 0
+#define FV_EINVAL (-1)  /* null or mis-sized argument, bad n, dt or step count, small arena */
+#define FV_EMESH (-2)   /* mesh fails validation (see fv_upload_mesh) */
+#define FV_ESTATE (-3)  /* state not positive or not finite, or not uploaded yet */
+#define FV_EHIP (-4)    /* a HIP runtime call failed; the message carries hipGetErrorString */
+#define FV_ENOMEM (-5)  /* host allocation failed */
+
+#define FV_ORDER_IDENTITY 0
+#define FV_ORDER_CM 1
+
+/*
+ * Device bytes the arena passed to fv_create must hold for n_cells cells
+ * (about 256 bytes per cell).  Returns 0 if n_cells <= 0 or too large for
+ * 32-bit cell indices.
+ */
+size_t fv_arena_bytes(int64_t n_cells);
+
+/*
+ * Create a context for a mesh of n_cells triangles (section 6.2.1).
+ *   gamma       ratio of specific heats (the paper uses 1.4; section 6.1);
+ *               must be finite and > 1.
+ *   d_arena     device pointer, 256-byte aligned, >= fv_arena_bytes(n_cells);
+ *               owned by the caller, must outlive the context.
+ *   hip_stream  hipStream_t (NULL = default stream) all work is issued on.
+ *   out         receives the context.
+ * FV_EINVAL on any bad argument.  Issues no HIP call.
+ */
+fv_status fv_create(int64_t n_cells, double gamma, void *d_arena, size_t arena_bytes,
+                    void *hip_stream, fv_ctx **out);
+
+/*
+ * Upload the mesh (section 6.2.1; data structures of section 3: node array
+ * plus fixed-degree connectivity and precomputed face normals, section 7).
+ *   nbr   host int32 [n][3]: nbr[i][f] is the cell across face f of cell i.
+ *   nrm   host double [n][3][2]: outward normal of face f of cell i, scaled
+ *         by the face length.
+ *   area  host double [n]: cell areas (V_T).
+ * Validation (FV_EMESH): every index in [0, n) and not i itself; every face
+ * (i, f) has a partner face (j, g) with nbr[j][g] == i and
+ * nrm[j][g] == -nrm[i][f] exactly (the mesh is closed, e.g. periodic);
+ * normals finite and non-zero; areas finite and > 0.
+ * Resets the cell order to the identity and invalidates the state.
+ * Synchronous with respect to the host arrays.
+ */
+fv_status fv_upload_mesh(fv_ctx *ctx, const int32_t *nbr, const double *nrm, const double *area);
+
+/*
+ * Upload the conserved state U = (rho, rho u, rho v, E) (section 6.1).
+ *   U  host double [n][4], in the numbering of the uploaded mesh.
+ * FV_ESTATE if any rho or p = (gamma - 1)(E - rho (u^2 + v^2) / 2) is not
+ * finite and > 0.  Requires an uploaded mesh.
+ */
+fv_status fv_upload_state(fv_ctx *ctx, const double *U);
+
+/*
+ * Same as fv_upload_state for a device array d_U [n][4] (original numbering)
+ * that is already resident in device memory; it is read on the stream, so
+ * it must stay valid until the stream reaches this point.  No validation of
+ * the values (they are not on the host).
+ */
+fv_status fv_upload_state_device(fv_ctx *ctx, const double *d_U);
+
+/*
+ * Renumber the cells for memory locality (section 4; motivation in
+ * sections 3 and 7.2) and permute every per-cell array on the device.
+ *   method    FV_ORDER_IDENTITY: the uploaded order.
+ *             FV_ORDER_CM: Cuthill-McKee.  Each connected component, taken
+ *             in order of its lowest cell id, is labelled breadth-first from a
+ *             pseudo-peripheral root (George-Liu search from that lowest id:
+ *             move to the last-level cell of minimum (degree, id) while the
+ *             eccentricity grows); the children of each labelled cell are
+ *             appended in (degree, id) order.  Ids are those of the uploaded
+ *             mesh, so the order depends only on the mesh.
+ *   perm_out  nullable host int32 [n]: perm_out[new] = uploaded id.
+ * The state (if uploaded) is carried over.  Results of fv_step do not
+ * depend on the order (bitwise).  Synchronises the stream.
+ */
+fv_status fv_renumber(fv_ctx *ctx, int32_t method, int32_t *perm_out);
+
+/*
+ * Advance n_steps forward-Euler steps of size dt (section 6.2.2, eqFWEuler
+ * and the update equation with the Lax-Friedrichs flux of eqCompFlux).
+ * n_steps >= 0; dt finite and > 0 (no CFL check: the caller picks dt).
+ * Asynchronous: returns once the kernels are queued on the stream.
+ */
+fv_status fv_step(fv_ctx *ctx, int32_t n_steps, double dt);
+
+/*
+ * Copy the state back in the numbering of the uploaded mesh.
+ *   U  host double [n][4].  Synchronises the stream.
+ */
+fv_status fv_download_state(fv_ctx *ctx, double *U);
+
+/*
+ * Same as fv_download_state into a device array d_U [n][4]; asynchronous on
+ * the stream.
+ */
+fv_status fv_download_state_device(fv_ctx *ctx, double *d_U);
+
+/*
+ * Check that every cell has finite rho > 0 and p > 0 (section 6.1 state
+ * admissibility).  Returns FV_OK or FV_ESTATE.  Synchronises the stream.
+ */
+fv_status fv_check_state(fv_ctx *ctx);
+
+/* Release the host-side context.  Does not touch the arena. */
+fv_status fv_destroy(fv_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *fv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FVGPU_H */

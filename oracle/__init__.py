@@ -12,7 +12,8 @@ import os
 
 import numpy as np
 
-from .build import LIB, build
+from .build import LIB
+from .build import build as build_oracle
 
 
 def _p(a: np.ndarray):
@@ -94,7 +95,7 @@ def default() -> Oracle:
     global _default
     if _default is None:
         if not os.path.exists(LIB):
-            build()
+            build_oracle()
         _default = Oracle(LIB)
     return _default
 

@@ -1,0 +1,32 @@
+"""MI355X (gfx950) explicit finite-volume Euler step on unstructured triangles.
+
+The computation lives in libfvgpu.so (HIP kernels behind the C ABI of
+include/fvgpu.h); this package is its thin Python binding.
+"""
+
+from .fvgpu import (  # noqa: F401
+    EXPORTS,
+    FV_EHIP,
+    FV_EINVAL,
+    FV_EMESH,
+    FV_ENOMEM,
+    FV_ESTATE,
+    FV_OK,
+    FV_ORDER_CM,
+    FV_ORDER_IDENTITY,
+    FVError,
+    Solver,
+    fv_arena_bytes,
+    fv_check_state,
+    fv_create,
+    fv_destroy,
+    fv_download_state,
+    fv_download_state_device,
+    fv_last_error,
+    fv_renumber,
+    fv_step,
+    fv_upload_mesh,
+    fv_upload_state,
+    fv_upload_state_device,
+    lib,
+)

@@ -1,0 +1,76 @@
+// Internal launchers shared by the host runtime (fv_runtime.hip) and the
+// kernel files.  Not part of the public ABI.
+//
+// Device layout of a mesh with n cells, leading dimension ld = n rounded up
+// to a multiple of 64 (so every sub-array starts 256-byte aligned):
+//   U       double4 [n]       (rho, rho u, rho v, E) per cell
+//   nb      int32  [3][ld]    neighbour across face f (structure of arrays)
+//   nrm     double [6][ld]    nx_0, ny_0, nx_1, ny_1, nx_2, ny_2
+//   inv_area double [ld]      1 / V_T
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fvk {
+
+constexpr int kStepBlock = 256;
+
+// One forward-Euler Lax-Friedrichs step over all cells: Un = U - dt/V sum F.
+hipError_t launch_step(int32_t n, int32_t ld, const double4 *U, double4 *Un, const int32_t *nb,
+                       const double *nrm, const double *inv_area, double dt, double gamma,
+                       hipStream_t s);
+
+// ---- renumbering --------------------------------------------------------
+struct CmResult {
+    int32_t count;       // cells labelled from the root (size of its component)
+    int32_t ecc;         // eccentricity of the root (levels - 1)
+    int32_t last_begin;  // first label of the last level
+    int32_t pick;        // last-level cell of minimum (degree, id)
+};
+
+// Breadth-first Cuthill-McKee labelling of the component of `root`, labels
+// starting at `base`.  label[] must hold -1 for every cell of the component.
+hipError_t launch_cm_component(int32_t n, int32_t ld, const int32_t *nb, int32_t root,
+                               int32_t base, int32_t *label, int32_t *perm, CmResult *res,
+                               hipStream_t s);
+
+// Lowest cell id >= from with label[id] == -1, or n if none; written to *out.
+hipError_t launch_find_unlabelled(int32_t n, const int32_t *label, int32_t from, int32_t *out,
+                                  hipStream_t s);
+
+// perm_dst[l] = perm_src[l] and label_dst[perm_src[l]] = l for l in [base, base + count).
+hipError_t launch_commit_labels(int32_t base, int32_t count, const int32_t *perm_src,
+                                int32_t *perm_dst, int32_t *label_dst, hipStream_t s);
+
+hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
+hipError_t launch_iota(int32_t *p, int32_t count, hipStream_t s);
+
+// ---- permutation gathers --------------------------------------------------
+// AoS host layouts to the device structure-of-arrays layout.
+hipError_t launch_nb_aos_to_soa(int32_t n, int32_t ld, const int32_t *aos, int32_t *soa,
+                                hipStream_t s);
+hipError_t launch_nrm_aos_to_soa(int32_t n, int32_t ld, const double *aos, double *soa,
+                                 hipStream_t s);
+
+// Working-order geometry from the uploaded mesh: for new cell l with
+// v = perm[l]: nb_w[f][l] = label[nb_o[f][v]], nrm_w[k][l] = nrm_o[k][v],
+// inv_area_w[l] = 1 / area_o[v].
+hipError_t launch_gather_geometry(int32_t n, int32_t ld, const int32_t *perm, const int32_t *label,
+                                  const int32_t *nb_o, const double *nrm_o, const double *area_o,
+                                  int32_t *nb_w, double *nrm_w, double *inv_area_w, hipStream_t s);
+
+// dst[l] = src[idx[l]]
+hipError_t launch_gather_state(int32_t n, const int32_t *idx, const double4 *src, double4 *dst,
+                               hipStream_t s);
+
+// dst[l] = src[idx_b[idx_a[l]]]
+hipError_t launch_gather_state2(int32_t n, const int32_t *idx_a, const int32_t *idx_b,
+                                const double4 *src, double4 *dst, hipStream_t s);
+
+// *flag = 1 if any cell has non-finite or non-positive rho or p (flag must be 0 before).
+hipError_t launch_check_state(int32_t n, const double4 *U, double gamma, int32_t *flag,
+                              hipStream_t s);
+
+}  // namespace fvk

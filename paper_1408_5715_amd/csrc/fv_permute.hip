@@ -1,0 +1,147 @@
+// K3: permutation gathers and layout changes (the paper's section 3 moves
+// the translation of global indices to the host, offline; here every
+// per-cell array is permuted on the device instead).
+//
+// All kernels are gathers: thread l reads from a computed index and writes
+// its own slot l, so no two threads write the same address.
+
+#include <cmath>
+
+#include "fv_internal.h"
+
+namespace fvk {
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(int64_t count)
+{
+    return (unsigned)((count + kBlock - 1) / kBlock);
+}
+
+__global__ void nb_aos_to_soa_kernel(int32_t n, int32_t ld, const int32_t *__restrict__ aos,
+                                     int32_t *__restrict__ soa)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+            soa[f * ld + i] = aos[3 * i + f];
+    }
+}
+
+__global__ void nrm_aos_to_soa_kernel(int32_t n, int32_t ld, const double *__restrict__ aos,
+                                      double *__restrict__ soa)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            soa[k * ld + i] = aos[6 * (int64_t)i + k];
+    }
+}
+
+__global__ void gather_geometry_kernel(int32_t n, int32_t ld, const int32_t *__restrict__ perm,
+                                       const int32_t *__restrict__ label,
+                                       const int32_t *__restrict__ nb_o,
+                                       const double *__restrict__ nrm_o,
+                                       const double *__restrict__ area_o,
+                                       int32_t *__restrict__ nb_w, double *__restrict__ nrm_w,
+                                       double *__restrict__ inv_area_w)
+{
+    const int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l >= n)
+        return;
+    const int v = perm[l];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+        nb_w[f * ld + l] = label[nb_o[f * ld + v]];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        nrm_w[k * ld + l] = nrm_o[k * ld + v];
+    inv_area_w[l] = 1.0 / area_o[v];
+}
+
+__global__ void gather_state_kernel(int32_t n, const int32_t *__restrict__ idx,
+                                    const double4 *__restrict__ src, double4 *__restrict__ dst)
+{
+    const int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l < n)
+        dst[l] = src[idx[l]];
+}
+
+__global__ void gather_state2_kernel(int32_t n, const int32_t *__restrict__ idx_a,
+                                     const int32_t *__restrict__ idx_b,
+                                     const double4 *__restrict__ src, double4 *__restrict__ dst)
+{
+    const int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l < n)
+        dst[l] = src[idx_b[idx_a[l]]];
+}
+
+__global__ void check_state_kernel(int32_t n, const double4 *__restrict__ U, double gamma,
+                                   int32_t *__restrict__ flag)
+{
+    const int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l >= n)
+        return;
+    const double4 u = U[l];
+    const double p = (gamma - 1.0) * (u.w - 0.5 * (u.y * u.y + u.z * u.z) / u.x);
+    const bool ok = isfinite(u.x) && isfinite(u.y) && isfinite(u.z) && isfinite(u.w) &&
+                    u.x > 0.0 && isfinite(p) && p > 0.0;
+    if (!ok)
+        *flag = 1;  // every writer stores the same value
+}
+
+}  // namespace
+
+hipError_t launch_nb_aos_to_soa(int32_t n, int32_t ld, const int32_t *aos, int32_t *soa,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(nb_aos_to_soa_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, ld, aos,
+                       soa);
+    return hipGetLastError();
+}
+
+hipError_t launch_nrm_aos_to_soa(int32_t n, int32_t ld, const double *aos, double *soa,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(nrm_aos_to_soa_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, ld, aos,
+                       soa);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_geometry(int32_t n, int32_t ld, const int32_t *perm, const int32_t *label,
+                                  const int32_t *nb_o, const double *nrm_o, const double *area_o,
+                                  int32_t *nb_w, double *nrm_w, double *inv_area_w, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_geometry_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, ld, perm,
+                       label, nb_o, nrm_o, area_o, nb_w, nrm_w, inv_area_w);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_state(int32_t n, const int32_t *idx, const double4 *src, double4 *dst,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_state_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, idx, src,
+                       dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_state2(int32_t n, const int32_t *idx_a, const int32_t *idx_b,
+                                const double4 *src, double4 *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_state2_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, idx_a,
+                       idx_b, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_state(int32_t n, const double4 *U, double gamma, int32_t *flag,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(check_state_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, U, gamma,
+                       flag);
+    return hipGetLastError();
+}
+
+}  // namespace fvk

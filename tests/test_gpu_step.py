@@ -1,0 +1,224 @@
+"""GPU parity of the HIP step, renumbering and permutation against the CPU
+oracle, through the C ABI.  Bar: per-component relative max error <= 1e-12
+(the oracle does not contract FMAs, the GPU does; see gpu_helpers.TOL);
+bitwise wherever the arithmetic is the same (re-runs, renumbering, resume)."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1408_5715_amd as fv
+from gpu_helpers import TOL, bumps_case, conserved_totals, log, rel_err, vortex_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def run_gpu(m, U0, dt, steps, order=fv.FV_ORDER_IDENTITY, chunks=None):
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        s.upload_state(U0)
+        perm = s.renumber(order) if order != fv.FV_ORDER_IDENTITY else None
+        for k in chunks or [steps]:
+            s.step(k, dt)
+        return s.download(), perm
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("N", [2, 3, 13, 64])
+def test_c1_parity_200_steps(torch, N):
+    """The 64 x 64 periodic vortex case (8,192 cells, CFL 0.4, 200 steps) and
+    smaller meshes below one workgroup and with a ragged last workgroup."""
+    log(f"parity N={N}")
+    m, U0, dt = vortex_case(N)
+    ref = oracle.step(m.nbr, m.nrm, m.area, U0, dt, 200)
+    got, _ = run_gpu(m, U0, dt, 200)
+    err = rel_err(got, ref)
+    assert np.all(err <= TOL), err
+
+
+def test_bit_stable_and_order_independent(torch):
+    m, U0, dt = vortex_case(64)
+    a, _ = run_gpu(m, U0, dt, 200)
+    b, _ = run_gpu(m, U0, dt, 200)
+    c, perm = run_gpu(m, U0, dt, 200, order=fv.FV_ORDER_CM)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
+    assert not np.array_equal(perm, np.arange(m.n))
+
+
+@pytest.mark.parametrize("N,seed", [(2, 1), (3, 2), (16, 5), (37, 2), (64, 2), (100, 8)])
+def test_gpu_cm_equals_oracle_cm(torch, N, seed):
+    log(f"cm N={N} seed={seed}")
+    m, U0, _ = vortex_case(N, perm_seed=seed)
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        perm = s.renumber(fv.FV_ORDER_CM)
+    finally:
+        s.close()
+    assert np.array_equal(perm, oracle.cm_order(m.nbr))
+
+
+def test_gpu_cm_disconnected_mesh(torch):
+    """Two meshes side by side (two components): the labelling restarts on
+    the component of the lowest unlabelled id, as in the oracle."""
+    a, _, _ = vortex_case(5, perm_seed=3)
+    b, _, _ = vortex_case(7, perm_seed=4)
+    n = a.n + b.n
+    nbr = np.concatenate([a.nbr, b.nbr + a.n])
+    nrm = np.concatenate([a.nrm, b.nrm])
+    area = np.concatenate([a.area, b.area])
+    rng = np.random.default_rng(0)
+    perm0 = rng.permutation(n)
+    inv0 = np.empty(n, dtype=np.int64)
+    inv0[perm0] = np.arange(n)
+    nbr = inv0[nbr[perm0]].astype(np.int32)
+    nrm, area = nrm[perm0], area[perm0]
+    s = fv.Solver(nbr, nrm, area)
+    try:
+        perm = s.renumber(fv.FV_ORDER_CM)
+    finally:
+        s.close()
+    assert np.array_equal(perm, oracle.cm_order(nbr))
+
+
+def test_renumber_identity_restores_order(torch):
+    m, U0, dt = vortex_case(16)
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        s.upload_state(U0)
+        s.step(5, dt)
+        s.renumber(fv.FV_ORDER_CM)
+        s.step(5, dt)
+        perm = s.renumber(fv.FV_ORDER_IDENTITY)
+        s.step(5, dt)
+        got = s.download()
+    finally:
+        s.close()
+    assert np.array_equal(perm, np.arange(m.n))
+    ref, _ = run_gpu(m, U0, dt, 15)
+    assert np.array_equal(got, ref)
+
+
+def test_checkpoint_resume_bitwise(torch):
+    m, U0, dt = vortex_case(32)
+    full, _ = run_gpu(m, U0, dt, 200, order=fv.FV_ORDER_CM)
+    half, _ = run_gpu(m, U0, dt, 100, order=fv.FV_ORDER_CM)
+    resumed, _ = run_gpu(m, half, dt, 100, order=fv.FV_ORDER_CM)
+    assert np.array_equal(full, resumed)
+    chunked, _ = run_gpu(m, U0, dt, 200, chunks=[1, 0, 99, 37, 63])
+    assert np.array_equal(full, chunked)
+
+
+def test_zero_steps_roundtrip(torch):
+    m, U0, dt = vortex_case(9)
+    got, _ = run_gpu(m, U0, dt, 0, order=fv.FV_ORDER_CM)
+    assert np.array_equal(got, U0)
+
+
+def test_every_cell_written(torch):
+    """Fill the output buffer with NaN bytes before a step: every cell must be
+    overwritten (no thread may skip its cell)."""
+    m, U0, dt = vortex_case(37)
+    ref = oracle.step(m.nbr, m.nrm, m.area, U0, dt, 1)
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        s.upload_state(U0)
+        s.renumber(fv.FV_ORDER_CM)
+        ld = (m.n + 63) // 64 * 64
+        # the second state buffer follows the first (32 bytes per cell)
+        s.arena[ld * 32: ld * 32 + m.n * 32].fill_(0xFF)
+        torch.cuda.synchronize()
+        s.step(1, dt)
+        got = s.download()
+    finally:
+        s.close()
+    assert np.all(np.isfinite(got))
+    assert np.all(rel_err(got, ref) <= TOL)
+
+
+def test_device_resident_state_roundtrip(torch):
+    m, U0, dt = vortex_case(20)
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        dU = torch.from_numpy(U0).cuda()
+        s.upload_state(dU)
+        s.renumber(fv.FV_ORDER_CM)
+        s.step(10, dt)
+        out = s.download_device()
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+    finally:
+        s.close()
+    ref, _ = run_gpu(m, U0, dt, 10)
+    assert np.array_equal(got, ref)
+
+
+def test_state_checks(torch):
+    m, U0, dt = vortex_case(16)
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        bad = U0.copy()
+        bad[3, 0] = -1.0
+        with pytest.raises(fv.FVError) as e:
+            s.upload_state(bad)
+        assert e.value.status == fv.FV_ESTATE
+        s.upload_state(U0)
+        s.check_state()
+        # a step 200 times past the CFL limit loses positivity
+        s.step(20, 200 * dt)
+        with pytest.raises(fv.FVError) as e:
+            s.check_state()
+        assert e.value.status == fv.FV_ESTATE
+    finally:
+        s.close()
+
+
+@pytest.mark.slow
+def test_c2_full_size(torch):
+    """The 1024 x 1024-quad mesh (2,097,152 cells) with the bump state: GPU in
+    random order and in GPU Cuthill-McKee order against the oracle after 5
+    steps (every cell compared), then 1000 steps: the two orders stay bitwise
+    equal and mass, momentum and energy are conserved to round-off."""
+    log("c2 mesh")
+    m, U0, dt = bumps_case(1024)
+    log("c2 oracle 5 steps")
+    ref = oracle.step(m.nbr, m.nrm, m.area, U0, dt, 5)
+    log("c2 gpu")
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        s.upload_state(U0)
+        s.step(5, dt)
+        a5 = s.download()
+        assert np.all(rel_err(a5, ref) <= TOL), rel_err(a5, ref)
+        s.upload_state(U0)
+        s.step(1000, dt)
+        a = s.download()
+        perm = s.renumber(fv.FV_ORDER_CM)
+        s.upload_state(U0)
+        s.step(5, dt)
+        b5 = s.download()
+        s.upload_state(U0)
+        s.step(1000, dt)
+        b = s.download()
+        s.check_state()
+    finally:
+        s.close()
+    assert np.array_equal(a5, b5)
+    assert np.array_equal(a, b)
+    log("c2 cm check")
+    assert np.array_equal(perm, oracle.cm_order(m.nbr))
+    t0 = conserved_totals(m, U0)
+    t1 = conserved_totals(m, a)
+    scale = np.sum(m.area[:, None] * np.abs(U0), axis=0)
+    assert np.all(np.abs(t1 - t0) / scale <= 1e-13), (t1 - t0) / scale
