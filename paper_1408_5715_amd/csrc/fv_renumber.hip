@@ -31,6 +31,7 @@ namespace {
 constexpr int kCmThreads = 1024;
 constexpr int kCmWaves = kCmThreads / 64;
 constexpr int kFrontierCap = 8000;  // two buffers plus scan space stay under 64 KiB of LDS
+constexpr int kPer = 3;             // frontier cells per thread and sweep
 
 // Block-wide exclusive scan over 1024 threads; *total receives the sum.
 __device__ __forceinline__ int block_exclusive_scan(int x, int *sh, int *total)
@@ -98,18 +99,18 @@ __device__ __forceinline__ int degree_of(int v, int a, int b, int c)
 }
 
 __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
-    int32_t n, int32_t ld, const int32_t *__restrict__ nb, int32_t root, int32_t base,
-    int32_t *__restrict__ label, int32_t *__restrict__ perm, CmResult *__restrict__ res)
+    int4 *__restrict__ rec, int32_t root, int32_t base, int32_t *__restrict__ perm,
+    CmResult *__restrict__ res)
 {
     __shared__ int32_t frontier[2][kFrontierCap];
     __shared__ int scan_sh[2 * kCmWaves + 1];
     __shared__ unsigned long long min_sh[kCmWaves];
 
-    const int32_t *nb0 = nb, *nb1 = nb + ld, *nb2 = nb + 2 * ld;
+    int32_t *label = reinterpret_cast<int32_t *>(rec);  // label of cell v: label[4 v + 3]
     const int tid = threadIdx.x;
 
     if (tid == 0) {
-        label[root] = base;
+        label[4 * root + 3] = base;
         perm[base] = root;
         frontier[0][0] = root;
     }
@@ -121,70 +122,101 @@ __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
     for (;;) {
         const int F = b - a;
         int produced = 0;  // children labelled so far in this level (block-uniform)
-        for (int c0 = 0; c0 < F; c0 += kCmThreads) {
-            const int t = c0 + tid;
-            int kid[3];
-            int kdeg[3];
-            int nk = 0;
-            if (t < F) {
-                const int v = t < kFrontierCap ? frontier[cur][t] : perm[a + t];
-                const int lv = a + t;
-                const int w3[3] = {nb0[v], nb1[v], nb2[v]};
+        // One sweep covers up to kCmThreads * kPer frontier cells; thread tid
+        // takes the contiguous run [tid * per, tid * per + per) of the sweep,
+        // so the scan of per-thread child counts keeps the label order.
+        for (int c0 = 0; c0 < F; c0 += kCmThreads * kPer) {
+            const int span = min(F - c0, kCmThreads * kPer);
+            const int per = (span + kCmThreads - 1) / kCmThreads;
+            const int first = tid * per;
+
+            // cells of the frontier and their records (neighbours)
+            int v[kPer], w[kPer][3];
+            bool ok[kPer];
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int t = first + k;
+                ok[k] = k < per && t < span;
+                const int ft = c0 + t;
+                v[k] = ok[k] ? (ft < kFrontierCap ? frontier[cur][ft] : perm[a + ft]) : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int4 r = ok[k] ? rec[v[k]] : make_int4(0, 0, 0, 0);
+                w[k][0] = r.x;
+                w[k][1] = r.y;
+                w[k][2] = r.z;
+            }
+            // records of the neighbours: their label and their neighbours
+            int lw[kPer][3], x[kPer][3][3];
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
-                    const int w = w3[f];
-                    bool cand = (w != v) && !(f >= 1 && w3[0] == w) && !(f == 2 && w3[1] == w);
-                    if (cand && label[w] != -1)
-                        cand = false;
-                    if (cand) {
-                        const int x0 = nb0[w], x1 = nb1[w], x2 = nb2[w];
-                        const int l0 = label[x0], l1 = label[x1], l2 = label[x2];
-                        int owner = INT_MAX;
-                        if (l0 >= a && l0 < b && l0 < owner)
-                            owner = l0;
-                        if (l1 >= a && l1 < b && l1 < owner)
-                            owner = l1;
-                        if (l2 >= a && l2 < b && l2 < owner)
-                            owner = l2;
-                        if (owner == lv) {
-                            kid[nk] = w;
-                            kdeg[nk] = degree_of(w, x0, x1, x2);
-                            ++nk;
-                        }
-                    }
-                }
-                // order the children by (degree, id)
-#pragma unroll
-                for (int p = 0; p < 2; ++p) {
-#pragma unroll
-                    for (int q = 0; q < 2 - p; ++q) {
-                        if (q + 1 < nk) {
-                            const bool swap = kdeg[q] > kdeg[q + 1] ||
-                                              (kdeg[q] == kdeg[q + 1] && kid[q] > kid[q + 1]);
-                            if (swap) {
-                                int tk = kid[q];
-                                kid[q] = kid[q + 1];
-                                kid[q + 1] = tk;
-                                int td = kdeg[q];
-                                kdeg[q] = kdeg[q + 1];
-                                kdeg[q + 1] = td;
-                            }
-                        }
-                    }
+                    const int4 r = ok[k] ? rec[w[k][f]] : make_int4(0, 0, 0, 0);
+                    x[k][f][0] = r.x;
+                    x[k][f][1] = r.y;
+                    x[k][f][2] = r.z;
+                    lw[k][f] = r.w;
                 }
             }
-            int chunk_total;
-            const int off = block_exclusive_scan(nk, scan_sh, &chunk_total);
-            for (int k = 0; k < nk; ++k) {
-                const int pos = produced + off + k;
-                const int lab = b + pos;
-                label[kid[k]] = lab;
-                perm[lab] = kid[k];
-                if (pos < kFrontierCap)
-                    frontier[cur ^ 1][pos] = kid[k];
+            // child flags and (degree, id) keys; a child's place among its
+            // siblings is the number of siblings with a smaller key
+            bool child[kPer][3];
+            int kdeg[kPer][3];
+            int nk[kPer];
+            int total = 0;
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int lv = a + c0 + first + k;
+                nk[k] = 0;
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const int ww = w[k][f];
+                    const bool cand = ok[k] && ww != v[k] && !(f >= 1 && w[k][0] == ww) &&
+                                      !(f == 2 && w[k][1] == ww) && lw[k][f] == -1;
+                    // owner: smallest frontier label among ww's neighbours (v[k]
+                    // itself is one of them, with label lv)
+                    int owner = INT_MAX;
+#pragma unroll
+                    for (int g = 0; g < 3; ++g) {
+                        const int xg = x[k][f][g];
+                        const int lx = (cand && xg != v[k]) ? label[4 * xg + 3] : lv;
+                        if (lx >= a && lx < b && lx < owner)
+                            owner = lx;
+                    }
+                    child[k][f] = cand && owner == lv;
+                    kdeg[k][f] = degree_of(ww, x[k][f][0], x[k][f][1], x[k][f][2]);
+                    nk[k] += child[k][f];
+                }
+                total += nk[k];
             }
-            produced += chunk_total;
-            // labels written by this chunk must be visible to the next chunk
+            int sweep_total;
+            int pos = produced + block_exclusive_scan(total, scan_sh, &sweep_total);
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    if (child[k][f]) {
+                        int rank = 0;
+#pragma unroll
+                        for (int g = 0; g < 3; ++g) {
+                            const bool before = kdeg[k][g] < kdeg[k][f] ||
+                                                (kdeg[k][g] == kdeg[k][f] && w[k][g] < w[k][f]);
+                            rank += (g != f && child[k][g] && before);
+                        }
+                        const int p = pos + rank;
+                        const int lab = b + p;
+                        label[4 * w[k][f] + 3] = lab;
+                        perm[lab] = w[k][f];
+                        if (p < kFrontierCap)
+                            frontier[cur ^ 1][p] = w[k][f];
+                    }
+                }
+                pos += nk[k];
+            }
+            produced += sweep_total;
+            // labels written by this sweep must be visible to the next one
             __threadfence_block();
             __syncthreads();
         }
@@ -200,7 +232,8 @@ __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
     unsigned long long best = ~0ull;
     for (int t = tid; t < b - a; t += kCmThreads) {
         const int v = t < kFrontierCap ? frontier[cur][t] : perm[a + t];
-        const int d = degree_of(v, nb0[v], nb1[v], nb2[v]);
+        const int4 r = rec[v];
+        const int d = degree_of(v, r.x, r.y, r.z);
         const unsigned long long key = ((unsigned long long)d << 32) | (unsigned)v;
         best = key < best ? key : best;
     }
@@ -231,6 +264,14 @@ __global__ __launch_bounds__(kCmThreads) void find_unlabelled_kernel(
         *out = n;
 }
 
+__global__ void build_records_kernel(int32_t n, int32_t ld, const int32_t *__restrict__ nb,
+                                     int4 *__restrict__ rec)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n)
+        rec[v] = make_int4(nb[v], nb[ld + v], nb[2 * ld + v], -1);
+}
+
 __global__ void commit_labels_kernel(int32_t base, int32_t count, const int32_t *__restrict__ src,
                                      int32_t *__restrict__ perm, int32_t *__restrict__ label)
 {
@@ -259,12 +300,19 @@ __global__ void iota_kernel(int32_t *__restrict__ p, int32_t count)
 
 }  // namespace
 
-hipError_t launch_cm_component(int32_t n, int32_t ld, const int32_t *nb, int32_t root,
-                               int32_t base, int32_t *label, int32_t *perm, CmResult *res,
-                               hipStream_t s)
+hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *rec,
+                                hipStream_t s)
 {
-    hipLaunchKernelGGL(cm_component_kernel, dim3(1), dim3(kCmThreads), 0, s, n, ld, nb, root, base,
-                       label, perm, res);
+    hipLaunchKernelGGL(build_records_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ld, nb,
+                       rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_cm_component(int4 *rec, int32_t root, int32_t base, int32_t *perm,
+                               CmResult *res, hipStream_t s)
+{
+    hipLaunchKernelGGL(cm_component_kernel, dim3(1), dim3(kCmThreads), 0, s, rec, root, base,
+                       perm, res);
     return hipGetLastError();
 }
 

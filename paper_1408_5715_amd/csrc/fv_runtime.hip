@@ -170,10 +170,9 @@ fv_status cm_order(fv_ctx *c)
 {
     const int32_t n = c->n;
     const size_t ld = (size_t)c->ld;
-    int32_t *labA = reinterpret_cast<int32_t *>(c->scratch);
-    int32_t *permA = labA + ld;
-    int32_t *labB = permA + ld;
-    int32_t *permB = labB + ld;
+    int4 *rec = reinterpret_cast<int4 *>(c->scratch);           // 16 B per cell
+    int32_t *permA = reinterpret_cast<int32_t *>(c->scratch + 16 * ld);
+    int32_t *permB = permA + ld;
     fvk::CmResult *dres = reinterpret_cast<fvk::CmResult *>(c->small);
     int32_t *dfind = reinterpret_cast<int32_t *>(c->small + 64);
 
@@ -192,22 +191,19 @@ fv_status cm_order(fv_ctx *c)
         scan_from = s;
 
         fvk::CmResult rr, rx;
-        HIP_TRY(fvk::launch_fill_i32(labA, -1, n, c->stream));
-        HIP_TRY(fvk::launch_cm_component(n, c->ld, c->nb_o, s, next, labA, permA, dres,
-                                         c->stream));
+        HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
+        HIP_TRY(fvk::launch_cm_component(rec, s, next, permA, dres, c->stream));
         HIP_TRY(hipMemcpyAsync(&rr, dres, sizeof(rr), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
         // George-Liu: move the root to the far end while the eccentricity grows
         for (;;) {
             const int32_t x = rr.pick;
-            HIP_TRY(fvk::launch_fill_i32(labB, -1, n, c->stream));
-            HIP_TRY(fvk::launch_cm_component(n, c->ld, c->nb_o, x, next, labB, permB, dres,
-                                             c->stream));
+            HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
+            HIP_TRY(fvk::launch_cm_component(rec, x, next, permB, dres, c->stream));
             HIP_TRY(hipMemcpyAsync(&rx, dres, sizeof(rx), hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(hipStreamSynchronize(c->stream));
             if (rx.ecc > rr.ecc) {
                 rr = rx;
-                std::swap(labA, labB);
                 std::swap(permA, permB);
             } else {
                 break;
