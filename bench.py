@@ -93,6 +93,8 @@ def main() -> int:
     ap.add_argument("--N", type=int, default=1024, help="quads per side")
     ap.add_argument("--cpu-sample-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -176,6 +178,14 @@ def main() -> int:
     torch.cuda.synchronize()
     random_step_s = a.elapsed_time(b) * 1e-3 / args.fv_steps
     s.close()
+
+    if args.probe_copy:
+        # known traffic: 256 MiB read and 256 MiB written per launch
+        src = torch.ones(32 * 2**20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
 
     traffic = None
     if MEASURED_TRAFFIC is not None and MEASURED_TRAFFIC.get("source_sha") == source_sha() \

@@ -30,14 +30,13 @@ struct CmResult {
     int32_t pick;        // last-level cell of minimum (degree, id)
 };
 
-// rec[v] = (nb_0[v], nb_1[v], nb_2[v], -1): the graph with a label slot,
-// one 16-byte record per cell.
+// rec[v] = (nb_0[v], nb_1[v], nb_2[v], -1): the graph with an empty label slot.
 hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *rec,
                                 hipStream_t s);
 
 // Breadth-first Cuthill-McKee labelling of the component of `root`, labels
-// starting at `base`, written to rec[v].w and perm[label].  rec[v].w must be
-// -1 for every cell of the component.
+// starting at `base`: perm[label] = cell, rec[cell].w = label.  rec must come
+// fresh from launch_build_records.
 hipError_t launch_cm_component(int4 *rec, int32_t root, int32_t base, int32_t *perm,
                                CmResult *res, hipStream_t s);
 

@@ -10,16 +10,25 @@
 // are the cells sorted by (owner label, degree, id).  The kernel builds the
 // same labelling one level at a time: every frontier cell finds the cells it
 // owns (an unlabelled neighbour w is owned by v when v has the smallest label
-// among w's neighbours inside the frontier), sorts its at most three children,
-// and a block-wide exclusive scan of the child counts gives every child its
-// label.  The result equals the sequential order exactly.
+// among w's neighbours inside the frontier), ranks its at most three
+// children, and a block-wide exclusive scan of the child counts gives every
+// child its label.  The result equals the sequential order exactly.
 //
 // One workgroup of 1024 threads runs all levels of a component in one
 // launch: levels are a few thousand cells wide, so the work per level is
-// latency-bound and a grid-wide barrier per level would only add latency.
-// The current and next frontier live in LDS (spilling to the global perm
-// array beyond kFrontierCap cells).  Every wave leaves the level loop on the
-// same block-uniform condition (an empty next level).
+// small, and a grid-wide barrier per level (which on this chip means writing
+// back and invalidating per-XCD L2 caches) would cost more than it saves.
+// Every wave leaves the level loop on the same block-uniform condition (an
+// empty next level).
+//
+// The graph is read as 16-byte records: three neighbours and the cell's
+// label (-1 while unlabelled), so one cache-line fetch answers both "is w
+// labelled" and "who are w's neighbours".  Frontier cells carry their
+// neighbour lists in LDS (fetched when they were discovered).  One CU runs
+// the whole labelling, and its cost is set by the number of scattered lane
+// requests per cell, so loads are issued only by the lanes that need them
+// (about 5.6 per frontier cell: three neighbour records and the labels of
+// the other neighbours of unlabelled cells).
 
 #include <climits>
 
@@ -30,7 +39,7 @@ namespace {
 
 constexpr int kCmThreads = 1024;
 constexpr int kCmWaves = kCmThreads / 64;
-constexpr int kFrontierCap = 8000;  // two buffers plus scan space stay under 64 KiB of LDS
+constexpr int kFrontierCap = 4096;  // frontier entries held in LDS per buffer (2 x 64 KiB)
 constexpr int kPer = 3;             // frontier cells per thread and sweep
 
 // Block-wide exclusive scan over 1024 threads; *total receives the sum.
@@ -98,11 +107,13 @@ __device__ __forceinline__ int degree_of(int v, int a, int b, int c)
     return d;
 }
 
+
+// rec[v] = (nb_0, nb_1, nb_2, label or -1).
 __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
     int4 *__restrict__ rec, int32_t root, int32_t base, int32_t *__restrict__ perm,
     CmResult *__restrict__ res)
 {
-    __shared__ int32_t frontier[2][kFrontierCap];
+    __shared__ int4 frontier[2][kFrontierCap];  // (cell, nb_0, nb_1, nb_2), in label order
     __shared__ int scan_sh[2 * kCmWaves + 1];
     __shared__ unsigned long long min_sh[kCmWaves];
 
@@ -110,10 +121,12 @@ __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
     const int tid = threadIdx.x;
 
     if (tid == 0) {
+        const int4 r = rec[root];
         label[4 * root + 3] = base;
         perm[base] = root;
-        frontier[0][0] = root;
+        frontier[0][0] = make_int4(root, r.x, r.y, r.z);
     }
+    __threadfence_block();
     __syncthreads();
 
     int a = base, b = base + 1;  // labels of the current level: [a, b)
@@ -130,7 +143,6 @@ __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
             const int per = (span + kCmThreads - 1) / kCmThreads;
             const int first = tid * per;
 
-            // cells of the frontier and their records (neighbours)
             int v[kPer], w[kPer][3];
             bool ok[kPer];
 #pragma unroll
@@ -138,14 +150,16 @@ __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
                 const int t = first + k;
                 ok[k] = k < per && t < span;
                 const int ft = c0 + t;
-                v[k] = ok[k] ? (ft < kFrontierCap ? frontier[cur][ft] : perm[a + ft]) : 0;
-            }
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int4 r = ok[k] ? rec[v[k]] : make_int4(0, 0, 0, 0);
-                w[k][0] = r.x;
-                w[k][1] = r.y;
-                w[k][2] = r.z;
+                int4 e = frontier[cur][(ok[k] && ft < kFrontierCap) ? ft : 0];
+                if (ok[k] && ft >= kFrontierCap) {
+                    const int c = perm[a + ft];
+                    const int4 r = rec[c];
+                    e = make_int4(c, r.x, r.y, r.z);
+                }
+                v[k] = e.x;
+                w[k][0] = e.y;
+                w[k][1] = e.z;
+                w[k][2] = e.w;
             }
             // records of the neighbours: their label and their neighbours
             int lw[kPer][3], x[kPer][3][3];
@@ -160,8 +174,25 @@ __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
                     lw[k][f] = r.w;
                 }
             }
-            // child flags and (degree, id) keys; a child's place among its
-            // siblings is the number of siblings with a smaller key
+            // an unlabelled neighbour ww is a child of v[k] when v[k] has the
+            // smallest label among ww's neighbours inside the frontier; the
+            // labels of ww's other neighbours are read for candidates only
+            bool cand[kPer][3];
+            int lx[kPer][3][3];
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const int ww = w[k][f];
+                    cand[k][f] = ok[k] && ww != v[k] && !(f >= 1 && w[k][0] == ww) &&
+                                 !(f == 2 && w[k][1] == ww) && lw[k][f] == -1;
+#pragma unroll
+                    for (int g = 0; g < 3; ++g) {
+                        const int xg = x[k][f][g];
+                        lx[k][f][g] = (cand[k][f] && xg != v[k]) ? label[4 * xg + 3] : -1;
+                    }
+                }
+            }
             bool child[kPer][3];
             int kdeg[kPer][3];
             int nk[kPer];
@@ -172,21 +203,15 @@ __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
                 nk[k] = 0;
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
-                    const int ww = w[k][f];
-                    const bool cand = ok[k] && ww != v[k] && !(f >= 1 && w[k][0] == ww) &&
-                                      !(f == 2 && w[k][1] == ww) && lw[k][f] == -1;
-                    // owner: smallest frontier label among ww's neighbours (v[k]
-                    // itself is one of them, with label lv)
                     int owner = INT_MAX;
 #pragma unroll
                     for (int g = 0; g < 3; ++g) {
-                        const int xg = x[k][f][g];
-                        const int lx = (cand && xg != v[k]) ? label[4 * xg + 3] : lv;
-                        if (lx >= a && lx < b && lx < owner)
-                            owner = lx;
+                        const int l = x[k][f][g] == v[k] ? lv : lx[k][f][g];
+                        if (l >= a && l < b && l < owner)
+                            owner = l;
                     }
-                    child[k][f] = cand && owner == lv;
-                    kdeg[k][f] = degree_of(ww, x[k][f][0], x[k][f][1], x[k][f][2]);
+                    child[k][f] = cand[k][f] && owner == lv;
+                    kdeg[k][f] = degree_of(w[k][f], x[k][f][0], x[k][f][1], x[k][f][2]);
                     nk[k] += child[k][f];
                 }
                 total += nk[k];
@@ -207,10 +232,11 @@ __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
                         }
                         const int p = pos + rank;
                         const int lab = b + p;
-                        label[4 * w[k][f] + 3] = lab;
-                        perm[lab] = w[k][f];
+                        const int c = w[k][f];
+                        label[4 * c + 3] = lab;
+                        perm[lab] = c;
                         if (p < kFrontierCap)
-                            frontier[cur ^ 1][p] = w[k][f];
+                            frontier[cur ^ 1][p] = make_int4(c, x[k][f][0], x[k][f][1], x[k][f][2]);
                     }
                 }
                 pos += nk[k];
@@ -231,10 +257,16 @@ __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
     // last level [a, b): cell of minimum (degree, id)
     unsigned long long best = ~0ull;
     for (int t = tid; t < b - a; t += kCmThreads) {
-        const int v = t < kFrontierCap ? frontier[cur][t] : perm[a + t];
-        const int4 r = rec[v];
-        const int d = degree_of(v, r.x, r.y, r.z);
-        const unsigned long long key = ((unsigned long long)d << 32) | (unsigned)v;
+        int4 e;
+        if (t < kFrontierCap) {
+            e = frontier[cur][t];
+        } else {
+            const int c = perm[a + t];
+            const int4 r = rec[c];
+            e = make_int4(c, r.x, r.y, r.z);
+        }
+        const int d = degree_of(e.x, e.y, e.z, e.w);
+        const unsigned long long key = ((unsigned long long)d << 32) | (unsigned)e.x;
         best = key < best ? key : best;
     }
     best = block_min_u64(best, min_sh);
@@ -264,6 +296,7 @@ __global__ __launch_bounds__(kCmThreads) void find_unlabelled_kernel(
         *out = n;
 }
 
+// rec[v] = (nb_0[v], nb_1[v], nb_2[v], -1): no cell labelled yet.
 __global__ void build_records_kernel(int32_t n, int32_t ld, const int32_t *__restrict__ nb,
                                      int4 *__restrict__ rec)
 {

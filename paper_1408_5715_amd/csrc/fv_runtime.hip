@@ -166,15 +166,25 @@ fv_status regather_geometry(fv_ctx *c)
 }
 
 // Cuthill-McKee labelling of the uploaded graph into c->perm / c->label.
+// Scratch use (bytes per cell): records 16, two candidate orders 4 + 4.
 fv_status cm_order(fv_ctx *c)
 {
     const int32_t n = c->n;
     const size_t ld = (size_t)c->ld;
-    int4 *rec = reinterpret_cast<int4 *>(c->scratch);           // 16 B per cell
-    int32_t *permA = reinterpret_cast<int32_t *>(c->scratch + 16 * ld);
-    int32_t *permB = permA + ld;
+    int4 *rec = reinterpret_cast<int4 *>(c->scratch);
+    int32_t *permA = reinterpret_cast<int32_t *>(rec + ld);  // best order so far
+    int32_t *permB = permA + ld;                             // trial order
     fvk::CmResult *dres = reinterpret_cast<fvk::CmResult *>(c->small);
     int32_t *dfind = reinterpret_cast<int32_t *>(c->small + 64);
+
+    // One level structure (and its labelling) from `root`.
+    auto pass = [&](int32_t root, int32_t base, int32_t *perm, fvk::CmResult *out) -> fv_status {
+        HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
+        HIP_TRY(fvk::launch_cm_component(rec, root, base, perm, dres, c->stream));
+        HIP_TRY(hipMemcpyAsync(out, dres, sizeof(*out), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        return FV_OK;
+    };
 
     HIP_TRY(fvk::launch_fill_i32(c->label, -1, n, c->stream));
     int32_t next = 0;
@@ -191,17 +201,12 @@ fv_status cm_order(fv_ctx *c)
         scan_from = s;
 
         fvk::CmResult rr, rx;
-        HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
-        HIP_TRY(fvk::launch_cm_component(rec, s, next, permA, dres, c->stream));
-        HIP_TRY(hipMemcpyAsync(&rr, dres, sizeof(rr), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
+        if (fv_status st = pass(s, next, permA, &rr))
+            return st;
         // George-Liu: move the root to the far end while the eccentricity grows
         for (;;) {
-            const int32_t x = rr.pick;
-            HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
-            HIP_TRY(fvk::launch_cm_component(rec, x, next, permB, dres, c->stream));
-            HIP_TRY(hipMemcpyAsync(&rx, dres, sizeof(rx), hipMemcpyDeviceToHost, c->stream));
-            HIP_TRY(hipStreamSynchronize(c->stream));
+            if (fv_status st = pass(rr.pick, next, permB, &rx))
+                return st;
             if (rx.ecc > rr.ecc) {
                 rr = rx;
                 std::swap(permA, permB);

@@ -224,3 +224,64 @@ def test_c2_full_size(torch):
     mom = np.sum(m.area * np.hypot(U0[:, 1], U0[:, 2]))
     scale = np.array([np.sum(m.area * U0[:, 0]), mom, mom, np.sum(m.area * U0[:, 3])])
     assert np.all(np.abs(t1 - t0) / scale <= 1e-13), (t1 - t0) / scale
+
+
+def double_tree_graph(depth: int):
+    """A 3-regular graph with very wide BFS levels: two ternary-rooted binary
+    trees whose leaves are joined in a ring (leaf i of one tree to leaves i and
+    i + 1 of the other).  Faces get placeholder normals that are exactly
+    antisymmetric, so the mesh validator accepts it; only the renumbering is
+    exercised on it."""
+    def tree(offset):
+        nodes = [[offset]]
+        edges = []
+        nid = offset + 1
+        for d in range(depth):
+            kids = 3 if d == 0 else 2
+            level = []
+            for p in nodes[-1]:
+                for _ in range(kids):
+                    edges.append((p, nid))
+                    level.append(nid)
+                    nid += 1
+            nodes.append(level)
+        return nodes[-1], edges, nid
+
+    leavesA, eA, nxt = tree(0)
+    leavesB, eB, n = tree(nxt)
+    edges = eA + eB
+    L = len(leavesA)
+    for i in range(L):
+        edges.append((leavesA[i], leavesB[i]))
+        edges.append((leavesA[i], leavesB[(i + 1) % L]))
+    adj = [[] for _ in range(n)]
+    for u, v in edges:
+        adj[u].append(v)
+        adj[v].append(u)
+    assert all(len(a) == 3 for a in adj)
+    nbr = np.array(adj, dtype=np.int32)
+    nrm = np.empty((n, 3, 2))
+    for u in range(n):
+        for f, v in enumerate(adj[u]):
+            sgn = 1.0 if u < v else -1.0
+            nrm[u, f] = (sgn * 1.0, sgn * 0.5)
+    return nbr, nrm, np.ones(n)
+
+
+def test_gpu_cm_wide_levels(torch):
+    """Levels far wider than the LDS tables hold (over 12,000 cells): the
+    renumbering falls back to labels in global memory and still matches the
+    sequential order exactly."""
+    nbr, nrm, area = double_tree_graph(13)
+    rng = np.random.default_rng(5)
+    p0 = rng.permutation(nbr.shape[0])
+    inv0 = np.empty_like(p0)
+    inv0[p0] = np.arange(p0.size)
+    nbr, nrm, area = inv0[nbr[p0]].astype(np.int32), nrm[p0], area[p0]
+    log(f"wide levels: {nbr.shape[0]} cells")
+    s = fv.Solver(nbr, nrm, area)
+    try:
+        perm = s.renumber(fv.FV_ORDER_CM)
+    finally:
+        s.close()
+    assert np.array_equal(perm, oracle.cm_order(nbr))
