@@ -33,10 +33,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic HBM bytes of one cell update (each per-cell array touched
-# once; the three neighbour states are reuse the renumbering keeps on chip):
-# read U 32 + neighbour ids 12 + face normals 48 + 1/area 8, write U 32.
-BYTES_PER_CELL_UPDATE = 132
+# Algorithmic HBM bytes of one cell update come from the library
+# (fv_bytes_per_update): each per-cell array touched once, the three
+# neighbour states counted as the cache reuse the renumbering provides.
+# General layout: read U 32 + neighbour ids 12 + normals 48 + 1/area 8,
+# write U 32 = 132; with 16-bit neighbour offsets and the derived third
+# normal (the layout of this workload after renumbering) 112.
 HBM_PEAK_GBS = 8000.0
 STEP_SOURCE = os.path.join(ROOT, "paper_1408_5715_amd", "csrc", "fv_step.hip")
 
@@ -158,17 +160,19 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
+    bytes_per_update = fv.fv_bytes_per_update(s.ctx)
     renum_ms = [a.elapsed_time(b) for a, b, _, _ in marks]
     step_ms = [b.elapsed_time(c) for _, b, c, _ in marks]
     down_ms = [c.elapsed_time(d) for _, _, c, d in marks]
     ms_per_job = wall * 1e3 / args.steps
     value = n * args.fv_steps * args.steps / wall
     step_kernel_s = float(np.mean(step_ms)) * 1e-3 / args.fv_steps
-    achieved = BYTES_PER_CELL_UPDATE * n / step_kernel_s / 1e9
+    achieved = bytes_per_update * n / step_kernel_s / 1e9
 
     # the same kernel on the random (identity) order, for the locality effect
     log("timing the step on the random order")
     fv.fv_renumber(s.ctx, fv.FV_ORDER_IDENTITY)
+    random_bytes_per_update = fv.fv_bytes_per_update(s.ctx)
     fv.fv_upload_state_device(s.ctx, dU0)
     fv.fv_step(s.ctx, 50, dt)
     a, b = ev(), ev()
@@ -227,7 +231,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "bytes_per_cell_update": BYTES_PER_CELL_UPDATE,
+            "bytes_per_cell_update": bytes_per_update,
             "avg_launch_us": step_kernel_s * 1e6,
         },
         "cpu_baseline": cpu,
@@ -238,6 +242,7 @@ def main() -> int:
             "step_only_cell_updates_per_s": n / step_kernel_s,
             "random_order_step_us": random_step_s * 1e6,
             "random_order_cell_updates_per_s": n / random_step_s,
+            "random_order_bytes_per_cell_update": random_bytes_per_update,
         },
     }
     print(json.dumps(rec), flush=True)

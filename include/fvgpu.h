@@ -140,6 +140,18 @@ fv_status fv_download_state(fv_ctx *ctx, double *U);
 fv_status fv_download_state_device(fv_ctx *ctx, double *d_U);
 
 /*
+ * Algorithmic device-memory bytes one cell update of fv_step moves with the
+ * current layout: the state read and written (32 + 32), 1/V_T (8), the
+ * neighbour indices (12 as 32-bit ids, or 8 as 16-bit offsets when the
+ * current order keeps every neighbour within 32767 cells) and the face
+ * normals (48, or 32 when every cell's normals satisfy n_2 = -(n_0 + n_1)
+ * exactly and the third is derived).  Neighbour states are counted as cache
+ * hits (the reuse the renumbering of section 4 provides).  Returns 0 on a
+ * null context or before the mesh is uploaded.
+ */
+int64_t fv_bytes_per_update(const fv_ctx *ctx);
+
+/*
  * Check that every cell has finite rho > 0 and p > 0 (section 6.1 state
  * admissibility).  Returns FV_OK or FV_ESTATE.  Synchronises the stream.
  */

@@ -17,6 +17,7 @@ from .fvgpu import (  # noqa: F401
     FVError,
     Solver,
     fv_arena_bytes,
+    fv_bytes_per_update,
     fv_check_state,
     fv_create,
     fv_destroy,

@@ -7,6 +7,7 @@
 //   nb      int32  [3][ld]    neighbour across face f (structure of arrays)
 //   nrm     double [6][ld]    nx_0, ny_0, nx_1, ny_1, nx_2, ny_2
 //   inv_area double [ld]      1 / V_T
+//   nb16    short4 [ld]       neighbour offsets j - i, when they fit in 16 bits
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,9 +19,16 @@ namespace fvk {
 constexpr int kStepBlock = 256;
 
 // One forward-Euler Lax-Friedrichs step over all cells: Un = U - dt/V sum F.
+// narrow: read neighbours from nb16 (16-bit offsets) instead of nb.
+// closed: take the third normal as -(n_0 + n_1) instead of reading it.
 hipError_t launch_step(int32_t n, int32_t ld, const double4 *U, double4 *Un, const int32_t *nb,
-                       const double *nrm, const double *inv_area, double dt, double gamma,
-                       hipStream_t s);
+                       const short4 *nb16, const double *nrm, const double *inv_area, double dt,
+                       double gamma, bool narrow, bool closed, hipStream_t s);
+
+// nb16[i] = (nb[0][i] - i, nb[1][i] - i, nb[2][i] - i, 0) as 16-bit offsets;
+// *too_far = 1 when some offset does not fit (it must be 0 before).
+hipError_t launch_narrow_offsets(int32_t n, int32_t ld, const int32_t *nb, short4 *nb16,
+                                 int32_t *too_far, hipStream_t s);
 
 // ---- renumbering --------------------------------------------------------
 struct CmResult {

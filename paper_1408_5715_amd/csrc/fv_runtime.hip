@@ -53,18 +53,19 @@ int64_t leading_dim(int64_t n)
 
 // Byte sizes of the arena regions for n cells (leading dimension ld).
 struct Layout {
-    size_t U, nb, nrm, area, idx, scratch, small, total;
+    size_t U, nb, nb16, nrm, area, idx, scratch, small, total;
     explicit Layout(int64_t n)
     {
         const size_t ld = (size_t)leading_dim(n);
         U = align_up(ld * 32);
         nb = align_up(ld * 3 * 4);
+        nb16 = align_up(ld * 8);
         nrm = align_up(ld * 6 * 8);
         area = align_up(ld * 8);
         idx = align_up(ld * 4);
         scratch = align_up(ld * 48);  // >= AoS normals (48 B), state (32 B), 4 CM arrays (16 B)
         small = kAlign;
-        total = 2 * U + 2 * nb + 2 * nrm + 2 * area + 2 * idx + scratch + small;
+        total = 2 * U + 2 * nb + nb16 + 2 * nrm + 2 * area + 2 * idx + scratch + small;
     }
 };
 
@@ -84,6 +85,7 @@ struct fv_ctx {
     double *nrm_o = nullptr;
     double *area_o = nullptr;
     int32_t *nb_w = nullptr;  // working (renumbered) order
+    short4 *nb16_w = nullptr; // ... as 16-bit offsets, valid when `narrow`
     double *nrm_w = nullptr;
     double *inv_area_w = nullptr;
     int32_t *perm = nullptr;   // perm[new] = uploaded id
@@ -93,6 +95,8 @@ struct fv_ctx {
 
     bool mesh_ready = false;
     bool state_ready = false;
+    bool closed = false;  // every cell: n_2 == -(n_0 + n_1) exactly
+    bool narrow = false;  // every neighbour offset of the working order fits in 16 bits
 };
 
 namespace {
@@ -157,11 +161,31 @@ fv_status validate_state(int64_t n, const double *U, double gamma)
     return FV_OK;
 }
 
-// Rebuild the working geometry for the current perm/label.
+// Every cell's third normal equals -(n_0 + n_1) in binary64 (true when the
+// normals are exact coordinate differences, as on snapped meshes).
+bool normals_closed(int64_t n, const double *nrm)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const double *q = nrm + 6 * i;
+        if (!(q[4] == -(q[0] + q[2]) && q[5] == -(q[1] + q[3])))
+            return false;
+    }
+    return true;
+}
+
+// Rebuild the working geometry for the current perm/label, and its 16-bit
+// neighbour offsets.  Synchronises the stream.
 fv_status regather_geometry(fv_ctx *c)
 {
     HIP_TRY(fvk::launch_gather_geometry(c->n, c->ld, c->perm, c->label, c->nb_o, c->nrm_o,
                                         c->area_o, c->nb_w, c->nrm_w, c->inv_area_w, c->stream));
+    int32_t *dflag = reinterpret_cast<int32_t *>(c->small + 192);
+    HIP_TRY(fvk::launch_fill_i32(dflag, 0, 1, c->stream));
+    HIP_TRY(fvk::launch_narrow_offsets(c->n, c->ld, c->nb_w, c->nb16_w, dflag, c->stream));
+    int32_t too_far = 1;
+    HIP_TRY(hipMemcpyAsync(&too_far, dflag, sizeof(too_far), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->narrow = too_far == 0;
     return FV_OK;
 }
 
@@ -271,6 +295,8 @@ fv_status fv_create(int64_t n_cells, double gamma, void *d_arena, size_t arena_b
     p += lay.nb;
     c->nb_w = reinterpret_cast<int32_t *>(p);
     p += lay.nb;
+    c->nb16_w = reinterpret_cast<short4 *>(p);
+    p += lay.nb16;
     c->nrm_o = reinterpret_cast<double *>(p);
     p += lay.nrm;
     c->nrm_w = reinterpret_cast<double *>(p);
@@ -302,6 +328,7 @@ fv_status fv_upload_mesh(fv_ctx *c, const int32_t *nbr, const double *nrm, const
     const size_t n = (size_t)c->n;
     c->mesh_ready = false;
     c->state_ready = false;
+    c->closed = normals_closed(c->n, nrm);
     HIP_TRY(hipMemcpyAsync(c->scratch, nbr, n * 3 * sizeof(int32_t), hipMemcpyHostToDevice,
                            c->stream));
     HIP_TRY(fvk::launch_nb_aos_to_soa(c->n, c->ld, reinterpret_cast<int32_t *>(c->scratch),
@@ -403,8 +430,9 @@ fv_status fv_step(fv_ctx *c, int32_t n_steps, double dt)
     if (!c->mesh_ready || !c->state_ready)
         return fail(FV_ESTATE, "upload the mesh and the state before stepping");
     for (int32_t s = 0; s < n_steps; ++s) {
-        HIP_TRY(fvk::launch_step(c->n, c->ld, c->U[c->cur], c->U[c->cur ^ 1], c->nb_w, c->nrm_w,
-                                 c->inv_area_w, dt, c->gamma, c->stream));
+        HIP_TRY(fvk::launch_step(c->n, c->ld, c->U[c->cur], c->U[c->cur ^ 1], c->nb_w, c->nb16_w,
+                                 c->nrm_w, c->inv_area_w, dt, c->gamma, c->narrow, c->closed,
+                                 c->stream));
         c->cur ^= 1;
     }
     return FV_OK;
@@ -441,6 +469,13 @@ fv_status fv_download_state_device(fv_ctx *c, double *d_U)
     HIP_TRY(fvk::launch_gather_state(c->n, c->label, c->U[c->cur], reinterpret_cast<double4 *>(d_U),
                                      c->stream));
     return FV_OK;
+}
+
+int64_t fv_bytes_per_update(const fv_ctx *c)
+{
+    if (!c || !c->mesh_ready)
+        return 0;
+    return 32 + 32 + 8 + (c->narrow ? 8 : 12) + (c->closed ? 32 : 48);
 }
 
 fv_status fv_check_state(fv_ctx *c)

@@ -2,12 +2,12 @@
 // (section 6.2.2 of the paper: semi-discrete form eqSemiDiscrete, forward
 // Euler eqFWEuler, Lax-Friedrichs flux eqCompFlux).
 //
-// One thread per cell.  The thread reads its own state, its three face
-// normals, its inverse area and the three neighbour indices, gathers the
-// three neighbour states and writes the updated state into the other buffer.
-// Nothing is scattered and nothing is accumulated across threads, so the
-// result of a cell depends only on its own inputs, in its own face order:
-// the same bits whatever the cell numbering or the launch shape.
+// One thread per cell.  The thread reads its own state, its face normals,
+// its inverse area and its neighbour indices, gathers the three neighbour
+// states and writes the updated state into the other buffer.  Nothing is
+// scattered and nothing is accumulated across threads, so the result of a
+// cell depends only on its own inputs, in its own face order: the same bits
+// whatever the cell numbering or the launch shape.
 //
 // The flux is evaluated without a face frame.  With n the length-scaled
 // outward normal, V = u n_x + v n_y = |n| u_n, the face-frame flux rotated
@@ -17,6 +17,19 @@
 // the rotation of the momentum jump back to x-y is the identity on U, so no
 // unit normal (and no division by |n|) is needed.  This is an exact
 // identity; only the rounding differs from the face-frame evaluation.
+//
+// The step is bound by HBM traffic, so two exact compressions of the
+// per-cell geometry are used when the mesh allows them (the paper makes the
+// same two points for its memory stream: indices can be narrowed once the
+// renumbering bounds the neighbour distance, section 3, and normals can be
+// derived instead of stored, section 7):
+//   - kNarrow: neighbour j of cell i stored as the 16-bit offset j - i
+//     (four shorts, 8 bytes) instead of three 32-bit indices; used when every
+//     offset fits, which the Cuthill-McKee order makes true on large meshes.
+//   - kClosed: the third normal read as -(n_0 + n_1) instead of from memory;
+//     used when every cell's stored normals satisfy n_2 == -(n_0 + n_1)
+//     exactly, so the value is bit-identical to the stored one.
+// Bytes per cell update: 132 (general), 112 with both.
 
 #include "fv_internal.h"
 
@@ -36,6 +49,33 @@ __device__ __forceinline__ int xcd_contiguous_block(int b, int nblocks)
     return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// 1 / a from the hardware reciprocal estimate refined by two Newton-Raphson
+// steps y <- y + y (1 - a y), each with a fused residual: the relative error
+// falls from the estimate's ~2^-26 to round-off.
+__device__ __forceinline__ double recip(double a)
+{
+    double y = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-a, y, 1.0);
+    return fma(y, e, y);
+}
+
+// sqrt(a) for a >= 0: two Newton-Raphson steps on the hardware reciprocal
+// square root estimate r <- r (3 - a r^2) / 2, then s = a r and one residual
+// correction s <- s + (a - s^2) r / 2.
+__device__ __forceinline__ double root(double a)
+{
+    double r = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a;
+    r = r * fma(-h * r, r, 1.5);
+    r = r * fma(-h * r, r, 1.5);
+    const double s = a * r;
+    const double e = fma(-s, s, a);
+    const double q = fma(e, 0.5 * r, s);
+    return a == 0.0 ? 0.0 : q;
+}
+
 struct Prim {
     double ir;  // 1 / rho
     double p;   // pressure
@@ -45,22 +85,47 @@ struct Prim {
 __device__ __forceinline__ Prim primitives(const double4 &U, double gamma)
 {
     Prim q;
-    q.ir = 1.0 / U.x;
+    q.ir = recip(U.x);
     // p = (gamma - 1) (E - rho |v|^2 / 2) with rho |v|^2 = (m_x^2 + m_y^2) / rho
     q.p = (gamma - 1.0) * (U.w - 0.5 * (U.y * U.y + U.z * U.z) * q.ir);
-    q.c = sqrt(gamma * q.p * q.ir);
+    q.c = root(gamma * q.p * q.ir);
     return q;
 }
 
+template <bool kNarrow, bool kClosed>
 __global__ __launch_bounds__(kStepBlock) void fv_step_kernel(
     int32_t n, int32_t ld, const double4 *__restrict__ U, double4 *__restrict__ Un,
-    const int32_t *__restrict__ nb, const double *__restrict__ nrm,
-    const double *__restrict__ inv_area, double dt, double gamma)
+    const int32_t *__restrict__ nb, const short4 *__restrict__ nb16,
+    const double *__restrict__ nrm, const double *__restrict__ inv_area, double dt, double gamma)
 {
     const int blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
     const int i = blk * kStepBlock + threadIdx.x;
     if (i >= n)
         return;
+
+    int js[3];
+    if constexpr (kNarrow) {
+        const short4 o = nb16[i];
+        js[0] = i + o.x;
+        js[1] = i + o.y;
+        js[2] = i + o.z;
+    } else {
+        js[0] = nb[i];
+        js[1] = nb[ld + i];
+        js[2] = nb[2 * ld + i];
+    }
+    double nxs[3], nys[3];
+    nxs[0] = nrm[i];
+    nys[0] = nrm[ld + i];
+    nxs[1] = nrm[2 * ld + i];
+    nys[1] = nrm[3 * ld + i];
+    if constexpr (kClosed) {
+        nxs[2] = -(nxs[0] + nxs[1]);
+        nys[2] = -(nys[0] + nys[1]);
+    } else {
+        nxs[2] = nrm[4 * ld + i];
+        nys[2] = nrm[5 * ld + i];
+    }
 
     const double4 Ui = U[i];
     const Prim L = primitives(Ui, gamma);
@@ -69,14 +134,12 @@ __global__ __launch_bounds__(kStepBlock) void fv_step_kernel(
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        const int j = nb[f * ld + i];
-        const double nx = nrm[(2 * f) * ld + i];
-        const double ny = nrm[(2 * f + 1) * ld + i];
-        const double4 Uj = U[j];
+        const double nx = nxs[f], ny = nys[f];
+        const double4 Uj = U[js[f]];
         const Prim R = primitives(Uj, gamma);
         const double uR = Uj.y * R.ir, vR = Uj.z * R.ir;
 
-        const double len = sqrt(nx * nx + ny * ny);
+        const double len = root(nx * nx + ny * ny);
         const double VL = uL * nx + vL * ny;
         const double VR = uR * nx + vR * ny;
         // |n| (|u_n bar| + c bar)
@@ -98,17 +161,53 @@ __global__ __launch_bounds__(kStepBlock) void fv_step_kernel(
     Un[i] = out;
 }
 
+// 16-bit neighbour offsets of the working order; *too_far = 1 (every writer
+// stores the same value) if some offset does not fit.
+__global__ void narrow_offsets_kernel(int32_t n, int32_t ld, const int32_t *__restrict__ nb,
+                                      short4 *__restrict__ nb16, int32_t *__restrict__ too_far)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n)
+        return;
+    const int o0 = nb[i] - i, o1 = nb[ld + i] - i, o2 = nb[2 * ld + i] - i;
+    const bool fits = o0 >= -32768 && o0 <= 32767 && o1 >= -32768 && o1 <= 32767 &&
+                      o2 >= -32768 && o2 <= 32767;
+    nb16[i] = make_short4((short)o0, (short)o1, (short)o2, 0);
+    if (!fits)
+        *too_far = 1;
+}
+
 }  // namespace
 
 hipError_t launch_step(int32_t n, int32_t ld, const double4 *U, double4 *Un, const int32_t *nb,
-                       const double *nrm, const double *inv_area, double dt, double gamma,
-                       hipStream_t s)
+                       const short4 *nb16, const double *nrm, const double *inv_area, double dt,
+                       double gamma, bool narrow, bool closed, hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
     const int blocks = (n + kStepBlock - 1) / kStepBlock;
-    hipLaunchKernelGGL(fv_step_kernel, dim3(blocks), dim3(kStepBlock), 0, s, n, ld, U, Un, nb,
-                       nrm, inv_area, dt, gamma);
+    if (narrow && closed)
+        hipLaunchKernelGGL((fv_step_kernel<true, true>), dim3(blocks), dim3(kStepBlock), 0, s, n,
+                           ld, U, Un, nb, nb16, nrm, inv_area, dt, gamma);
+    else if (narrow)
+        hipLaunchKernelGGL((fv_step_kernel<true, false>), dim3(blocks), dim3(kStepBlock), 0, s, n,
+                           ld, U, Un, nb, nb16, nrm, inv_area, dt, gamma);
+    else if (closed)
+        hipLaunchKernelGGL((fv_step_kernel<false, true>), dim3(blocks), dim3(kStepBlock), 0, s, n,
+                           ld, U, Un, nb, nb16, nrm, inv_area, dt, gamma);
+    else
+        hipLaunchKernelGGL((fv_step_kernel<false, false>), dim3(blocks), dim3(kStepBlock), 0, s, n,
+                           ld, U, Un, nb, nb16, nrm, inv_area, dt, gamma);
+    return hipGetLastError();
+}
+
+hipError_t launch_narrow_offsets(int32_t n, int32_t ld, const int32_t *nb, short4 *nb16,
+                                 int32_t *too_far, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(narrow_offsets_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ld, nb,
+                       nb16, too_far);
     return hipGetLastError();
 }
 

@@ -28,8 +28,8 @@ FV_ORDER_CM = 1
 # every symbol include/fvgpu.h declares
 EXPORTS = (
     "fv_arena_bytes", "fv_create", "fv_upload_mesh", "fv_upload_state", "fv_upload_state_device",
-    "fv_renumber", "fv_step", "fv_download_state", "fv_download_state_device", "fv_check_state",
-    "fv_destroy", "fv_last_error",
+    "fv_renumber", "fv_step", "fv_download_state", "fv_download_state_device",
+    "fv_bytes_per_update", "fv_check_state", "fv_destroy", "fv_last_error",
 )
 
 
@@ -62,12 +62,14 @@ def lib() -> ctypes.CDLL:
         L.fv_step.argtypes = [vp, i32, dbl]
         L.fv_download_state.argtypes = [vp, vp]
         L.fv_download_state_device.argtypes = [vp, vp]
+        L.fv_bytes_per_update.argtypes = [vp]
+        L.fv_bytes_per_update.restype = i64
         L.fv_check_state.argtypes = [vp]
         L.fv_destroy.argtypes = [vp]
         L.fv_last_error.argtypes = []
         L.fv_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("fv_arena_bytes", "fv_last_error"):
+            if name not in ("fv_arena_bytes", "fv_last_error", "fv_bytes_per_update"):
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -135,6 +137,10 @@ def fv_download_state_device(ctx: int, d_U) -> None:
     _check(lib().fv_download_state_device(ctx, _ptr(d_U)))
 
 
+def fv_bytes_per_update(ctx: int) -> int:
+    return int(lib().fv_bytes_per_update(ctx))
+
+
 def fv_check_state(ctx: int) -> None:
     _check(lib().fv_check_state(ctx))
 
@@ -193,6 +199,9 @@ class Solver:
 
     def check_state(self) -> None:
         fv_check_state(self.ctx)
+
+    def bytes_per_update(self) -> int:
+        return fv_bytes_per_update(self.ctx)
 
     def close(self) -> None:
         if getattr(self, "ctx", None):

@@ -285,3 +285,41 @@ def test_gpu_cm_wide_levels(torch):
     finally:
         s.close()
     assert np.array_equal(perm, oracle.cm_order(nbr))
+
+
+def open_normals(m, fraction=0.05, seed=9):
+    """Scale the normals of some face pairs by (1 + 2^-20) on both sides:
+    antisymmetry stays exact, closure n_2 = -(n_0 + n_1) no longer holds."""
+    nrm = m.nrm.copy()
+    rng = np.random.default_rng(seed)
+    for i in rng.choice(m.n, max(1, int(fraction * m.n)), replace=False):
+        f = 0
+        j = m.nbr[i, f]
+        g = [g for g in range(3) if m.nbr[j, g] == i and np.all(m.nrm[j, g] == -m.nrm[i, f])][0]
+        nrm[i, f] *= 1.0 + 2.0**-20
+        nrm[j, g] = -nrm[i, f]
+    return nrm
+
+
+@pytest.mark.parametrize("closed", [True, False])
+@pytest.mark.parametrize("order", [fv.FV_ORDER_IDENTITY, fv.FV_ORDER_CM])
+def test_layout_variants(torch, closed, order):
+    """All four geometry layouts of the step (16-bit offsets or 32-bit ids,
+    derived or stored third normal) agree with the oracle, and runs that
+    differ only in the cell order agree bitwise."""
+    N = 160  # 51,200 cells: a random order has offsets beyond 16 bits, CM's do not
+    m, U0, dt = vortex_case(N)
+    nrm = m.nrm if closed else open_normals(m)
+    log(f"layout closed={closed} order={order}")
+    ref = oracle.step(m.nbr, nrm, m.area, U0, dt, 100)
+    s = fv.Solver(m.nbr, nrm, m.area)
+    try:
+        s.upload_state(U0)
+        s.renumber(order)
+        want = 32 + 32 + 8 + (8 if order == fv.FV_ORDER_CM else 12) + (32 if closed else 48)
+        assert s.bytes_per_update() == want
+        s.step(100, dt)
+        got = s.download()
+    finally:
+        s.close()
+    assert np.all(rel_err(got, ref) <= TOL), rel_err(got, ref)
