@@ -42,10 +42,15 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 STEP_SOURCE = os.path.join(ROOT, "paper_1408_5715_amd", "csrc", "fv_step.hip")
 
-# HBM traffic of one step launch on this workload, from rocprofv3 --pmc
-# FETCH_SIZE / WRITE_SIZE runs (profiles/fv_step_c2_counters.md), valid only
-# for the step kernel source with this SHA-256.
-MEASURED_TRAFFIC = None
+# HBM traffic of one step launch on this workload (renumbered order, 112-byte
+# layout), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs, each scaled
+# by what the counter reads for a plain 256 MiB copy in the same run (x2.000
+# and x1.000).  Valid only for the step kernel source with this SHA-256.
+MEASURED_TRAFFIC = {
+    "source_sha": "71e111d5fe51c1c028c8a8a1720e61192864322c089b286f67504476711d4442",
+    "cells": 2097152,
+    "bytes_per_launch": 235933620,  # fetch 168,825,780 + write 67,107,840
+}
 
 
 def log(msg: str) -> None:
@@ -95,6 +100,8 @@ def main() -> int:
     ap.add_argument("--N", type=int, default=1024, help="quads per side")
     ap.add_argument("--cpu-sample-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-random", action="store_true",
+                    help="skip timing the step on the random (not renumbered) order")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -170,17 +177,20 @@ def main() -> int:
     achieved = bytes_per_update * n / step_kernel_s / 1e9
 
     # the same kernel on the random (identity) order, for the locality effect
-    log("timing the step on the random order")
-    fv.fv_renumber(s.ctx, fv.FV_ORDER_IDENTITY)
-    random_bytes_per_update = fv.fv_bytes_per_update(s.ctx)
-    fv.fv_upload_state_device(s.ctx, dU0)
-    fv.fv_step(s.ctx, 50, dt)
-    a, b = ev(), ev()
-    a.record(stream)
-    fv.fv_step(s.ctx, args.fv_steps, dt)
-    b.record(stream)
-    torch.cuda.synchronize()
-    random_step_s = a.elapsed_time(b) * 1e-3 / args.fv_steps
+    random_step_s = float("nan")
+    random_bytes_per_update = None
+    if not args.skip_random:
+        log("timing the step on the random order")
+        fv.fv_renumber(s.ctx, fv.FV_ORDER_IDENTITY)
+        random_bytes_per_update = fv.fv_bytes_per_update(s.ctx)
+        fv.fv_upload_state_device(s.ctx, dU0)
+        fv.fv_step(s.ctx, 50, dt)
+        a, b = ev(), ev()
+        a.record(stream)
+        fv.fv_step(s.ctx, args.fv_steps, dt)
+        b.record(stream)
+        torch.cuda.synchronize()
+        random_step_s = a.elapsed_time(b) * 1e-3 / args.fv_steps
     s.close()
 
     if args.probe_copy:
@@ -240,8 +250,8 @@ def main() -> int:
             "steps_ms": float(np.median(step_ms)),
             "download_ms": float(np.median(down_ms)),
             "step_only_cell_updates_per_s": n / step_kernel_s,
-            "random_order_step_us": random_step_s * 1e6,
-            "random_order_cell_updates_per_s": n / random_step_s,
+            "random_order_step_us": None if args.skip_random else random_step_s * 1e6,
+            "random_order_cell_updates_per_s": None if args.skip_random else n / random_step_s,
             "random_order_bytes_per_cell_update": random_bytes_per_update,
         },
     }
