@@ -87,6 +87,22 @@ fv_status fv_create(int64_t n_cells, double gamma, void *d_arena, size_t arena_b
 fv_status fv_upload_mesh(fv_ctx *ctx, const int32_t *nbr, const double *nrm, const double *area);
 
 /*
+ * Upload a batch of independent closed meshes as one mesh of n_cells cells
+ * (the step of section 6.2.2 applied to each mesh; every mesh keeps its own
+ * time step, see fv_step_batch).
+ *   n_meshes    1 .. 65536.
+ *   mesh_begin  host int64 [n_meshes + 1]: mesh k owns cells
+ *               [mesh_begin[k], mesh_begin[k+1]); mesh_begin[0] = 0,
+ *               mesh_begin[n_meshes] = n_cells, strictly increasing.
+ *   nbr, nrm, area  as for fv_upload_mesh, in batch numbering.
+ * Validation as for fv_upload_mesh (FV_EMESH), plus FV_EMESH if a face joins
+ * two meshes and FV_EINVAL for bad offsets.  Renumbering then keeps every
+ * mesh in its own range of cells.
+ */
+fv_status fv_upload_batch(fv_ctx *ctx, int32_t n_meshes, const int64_t *mesh_begin,
+                          const int32_t *nbr, const double *nrm, const double *area);
+
+/*
  * Upload the conserved state U = (rho, rho u, rho v, E) (section 6.1).
  *   U  host double [n][4], in the numbering of the uploaded mesh.
  * FV_ESTATE if any rho or p = (gamma - 1)(E - rho (u^2 + v^2) / 2) is not
@@ -112,7 +128,8 @@ fv_status fv_upload_state_device(fv_ctx *ctx, const double *d_U);
  *             move to the last-level cell of minimum (degree, id) while the
  *             eccentricity grows); the children of each labelled cell are
  *             appended in (degree, id) order.  Ids are those of the uploaded
- *             mesh, so the order depends only on the mesh.
+ *             mesh, so the order depends only on the mesh.  Runs entirely on
+ *             the device, one workgroup per mesh of a batch.
  *   perm_out  nullable host int32 [n]: perm_out[new] = uploaded id.
  * The state (if uploaded) is carried over.  Results of fv_step do not
  * depend on the order (bitwise).  Synchronises the stream.
@@ -126,6 +143,35 @@ fv_status fv_renumber(fv_ctx *ctx, int32_t method, int32_t *perm_out);
  * Asynchronous: returns once the kernels are queued on the stream.
  */
 fv_status fv_step(fv_ctx *ctx, int32_t n_steps, double dt);
+
+/*
+ * fv_step for a batch: mesh k advances with time step dt[k].
+ *   dt  host double [n_meshes], finite and > 0.
+ * All meshes advance in one launch per step.  Asynchronous like fv_step.
+ */
+fv_status fv_step_batch(fv_ctx *ctx, int32_t n_steps, const double *dt);
+
+/*
+ * Launch shape of the step kernel (no effect on results, which are bitwise
+ * independent of it).
+ *   block      workgroup size: 128, 256 (default) or 512 cells.
+ *   grid       0 (default): one workgroup per tile of `block` cells;
+ *              g > 0: g persistent workgroups striding over the tiles.
+ *   use_graph  1: fv_step / fv_step_batch capture their launches into a HIP
+ *              graph (cached for the same step count and layout) and launch
+ *              it as one unit on the context's stream; 0 (default): launch
+ *              kernel by kernel.
+ * FV_EINVAL for other values.
+ */
+fv_status fv_set_launch(fv_ctx *ctx, int32_t block, int32_t grid, int32_t use_graph);
+
+/*
+ * Number of labelling passes (breadth-first sweeps of section 4's
+ * renumbering, including the pseudo-peripheral search) each mesh took in the
+ * last fv_renumber with FV_ORDER_CM.
+ *   passes  host int32 [n_meshes].  Synchronises the stream.
+ */
+fv_status fv_renumber_passes(fv_ctx *ctx, int32_t *passes);
 
 /*
  * Copy the state back in the numbering of the uploaded mesh.

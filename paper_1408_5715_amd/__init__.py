@@ -25,6 +25,10 @@ from .fvgpu import (  # noqa: F401
     fv_download_state_device,
     fv_last_error,
     fv_renumber,
+    fv_renumber_passes,
+    fv_set_launch,
+    fv_step_batch,
+    fv_upload_batch,
     fv_step,
     fv_upload_mesh,
     fv_upload_state,

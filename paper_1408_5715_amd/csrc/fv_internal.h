@@ -16,14 +16,20 @@
 
 namespace fvk {
 
-constexpr int kStepBlock = 256;
 
-// One forward-Euler Lax-Friedrichs step over all cells: Un = U - dt/V sum F.
+// One forward-Euler Lax-Friedrichs step over all cells: Un = U - coef sum F
+// with coef[i] = dt / V_i.
 // narrow: read neighbours from nb16 (16-bit offsets) instead of nb.
 // closed: take the third normal as -(n_0 + n_1) instead of reading it.
+// block: 128, 256 or 512 threads; grid: 0 = one workgroup per tile of
+// `block` cells, else that many persistent workgroups.
 hipError_t launch_step(int32_t n, int32_t ld, const double4 *U, double4 *Un, const int32_t *nb,
-                       const short4 *nb16, const double *nrm, const double *inv_area, double dt,
-                       double gamma, bool narrow, bool closed, hipStream_t s);
+                       const short4 *nb16, const double *nrm, const double *coef, double gamma,
+                       bool narrow, bool closed, int block, int grid, hipStream_t s);
+
+// coef[i] = dt[s] * inv_area[i], s the segment of cell i.
+hipError_t launch_coef(int32_t n, int32_t n_seg, const int64_t *seg, const double *dt,
+                       const double *inv_area, double *coef, hipStream_t s);
 
 // nb16[i] = (nb[0][i] - i, nb[1][i] - i, nb[2][i] - i, 0) as 16-bit offsets;
 // *too_far = 1 when some offset does not fit (it must be 0 before).
@@ -31,30 +37,18 @@ hipError_t launch_narrow_offsets(int32_t n, int32_t ld, const int32_t *nb, short
                                  int32_t *too_far, hipStream_t s);
 
 // ---- renumbering --------------------------------------------------------
-struct CmResult {
-    int32_t count;       // cells labelled from the root (size of its component)
-    int32_t ecc;         // eccentricity of the root (levels - 1)
-    int32_t last_begin;  // first label of the last level
-    int32_t pick;        // last-level cell of minimum (degree, id)
-};
-
 // rec[v] = (nb_0[v], nb_1[v], nb_2[v], -1): the graph with an empty label slot.
 hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *rec,
                                 hipStream_t s);
 
-// Breadth-first Cuthill-McKee labelling of the component of `root`, labels
-// starting at `base`: perm[label] = cell, rec[cell].w = label.  rec must come
-// fresh from launch_build_records.
-hipError_t launch_cm_component(int4 *rec, int32_t root, int32_t base, int32_t *perm,
-                               CmResult *res, hipStream_t s);
-
-// Lowest cell id >= from with label[id] == -1, or n if none; written to *out.
-hipError_t launch_find_unlabelled(int32_t n, const int32_t *label, int32_t from, int32_t *out,
-                                  hipStream_t s);
-
-// perm_dst[l] = perm_src[l] and label_dst[perm_src[l]] = l for l in [base, base + count).
-hipError_t launch_commit_labels(int32_t base, int32_t count, const int32_t *perm_src,
-                                int32_t *perm_dst, int32_t *label_dst, hipStream_t s);
+// Cuthill-McKee order of every segment [seg[k], seg[k+1]) (device array of
+// n_seg + 1 offsets; no face crosses a segment), one workgroup per segment:
+// perm[label] = cell, label[cell] = label.  rec comes fresh from
+// launch_build_records, permA / permB are scratch of n entries, passes[k]
+// receives the number of labelling passes of segment k.
+hipError_t launch_cm_segments(int4 *rec, int32_t n, int32_t n_seg, const int64_t *seg,
+                              int32_t *permA, int32_t *permB, int32_t *perm, int32_t *label,
+                              int32_t *passes, hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_iota(int32_t *p, int32_t count, hipStream_t s);

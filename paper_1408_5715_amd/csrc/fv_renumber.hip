@@ -14,10 +14,12 @@
 // children, and a block-wide exclusive scan of the child counts gives every
 // child its label.  The result equals the sequential order exactly.
 //
-// One workgroup of 1024 threads runs all levels of a component in one
-// launch: levels are a few thousand cells wide, so the work per level is
-// small, and a grid-wide barrier per level (which on this chip means writing
-// back and invalidating per-XCD L2 caches) would cost more than it saves.
+// One workgroup of 1024 threads labels a whole mesh in one launch (all
+// levels, the pseudo-peripheral search and every component): levels are a
+// few thousand cells wide, so the work per level is small, and a grid-wide
+// barrier per level (which on this chip means writing back and invalidating
+// per-XCD L2 caches) would cost more than it saves.  A batch of independent
+// meshes runs one such workgroup per mesh, side by side.
 // Every wave leaves the level loop on the same block-uniform condition (an
 // empty next level).
 //
@@ -108,14 +110,28 @@ __device__ __forceinline__ int degree_of(int v, int a, int b, int c)
 }
 
 
-// rec[v] = (nb_0, nb_1, nb_2, label or -1).
-__global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
-    int4 *__restrict__ rec, int32_t root, int32_t base, int32_t *__restrict__ perm,
-    CmResult *__restrict__ res)
+struct PassResult {
+    int count;  // cells labelled (the component of the root)
+    int ecc;    // eccentricity of the root
+    int pick;   // last-level cell of minimum (degree, id)
+};
+
+// LDS of one labelling pass.
+struct PassLds {
+    int4 frontier[2][kFrontierCap];  // (cell, nb_0, nb_1, nb_2), in label order
+    int scan[2 * kCmWaves + 1];
+    unsigned long long minv[kCmWaves];
+};
+
+// One breadth-first Cuthill-McKee labelling of the component of `root`,
+// labels from `base`: rec[v].w = label, perm[label] = v.  rec[v].w must be
+// -1 for every cell of the component.  Called by all threads of the block.
+__device__ PassResult cm_pass(int4 *__restrict__ rec, int32_t root, int32_t base,
+                              int32_t *__restrict__ perm, PassLds &lds)
 {
-    __shared__ int4 frontier[2][kFrontierCap];  // (cell, nb_0, nb_1, nb_2), in label order
-    __shared__ int scan_sh[2 * kCmWaves + 1];
-    __shared__ unsigned long long min_sh[kCmWaves];
+    int4 (&frontier)[2][kFrontierCap] = lds.frontier;
+    int *scan_sh = lds.scan;
+    unsigned long long *min_sh = lds.minv;
 
     int32_t *label = reinterpret_cast<int32_t *>(rec);  // label of cell v: label[4 v + 3]
     const int tid = threadIdx.x;
@@ -270,30 +286,94 @@ __global__ __launch_bounds__(kCmThreads) void cm_component_kernel(
         best = key < best ? key : best;
     }
     best = block_min_u64(best, min_sh);
-    if (tid == 0) {
-        res->count = b - base;
-        res->ecc = ecc;
-        res->last_begin = a;
-        res->pick = (int32_t)(best & 0xffffffffu);
-    }
+    PassResult r;
+    r.count = b - base;
+    r.ecc = ecc;
+    r.pick = (int32_t)(best & 0xffffffffu);
+    return r;
 }
 
-__global__ __launch_bounds__(kCmThreads) void find_unlabelled_kernel(
-    int32_t n, const int32_t *__restrict__ label, int32_t from, int32_t *__restrict__ out)
+// Cuthill-McKee order of each segment [seg[s], seg[s+1]) of the graph, one
+// workgroup per segment (no face may cross a segment boundary).  Within a
+// segment, components are taken in order of their lowest id; each one's root
+// is found by the George-Liu search from that id (label from the current
+// root, take the last level's cell of minimum (degree, id), relabel from it,
+// keep it while the eccentricity grows).  Output perm[label] = cell; permA
+// and permB are scratch of n entries.  A cell's record label is -1 until the
+// first pass reaches it, so the next component's root is the lowest cell
+// still at -1.  Every loop below ends on a block-uniform condition: each
+// component is labelled in full before the next starts, and the search
+// moves only while the eccentricity, bounded by the segment size, strictly
+// grows.
+__global__ __launch_bounds__(kCmThreads) void cm_segments_kernel(
+    int4 *__restrict__ rec, const int64_t *__restrict__ seg, int32_t *__restrict__ permA,
+    int32_t *__restrict__ permB, int32_t *__restrict__ perm, int32_t *__restrict__ passes)
 {
-    __shared__ unsigned long long min_sh[kCmWaves];
-    for (int c0 = from; c0 < n; c0 += kCmThreads) {
-        const int t = c0 + threadIdx.x;
-        const unsigned long long key = (t < n && label[t] == -1) ? (unsigned long long)t : ~0ull;
-        const unsigned long long m = block_min_u64(key, min_sh);
-        if (m != ~0ull) {
-            if (threadIdx.x == 0)
-                *out = (int32_t)m;
-            return;  // block-uniform exit
+    __shared__ PassLds lds;
+    const int tid = threadIdx.x;
+    const int s0 = (int)seg[blockIdx.x], s1 = (int)seg[blockIdx.x + 1];
+    int32_t *rlabel = reinterpret_cast<int32_t *>(rec);
+    int npass = 0;
+    int next = s0;
+    int scan_from = s0;
+    while (next < s1) {
+        // lowest cell of the segment no pass has reached
+        int root = s1;
+        for (int c0 = scan_from; c0 < s1 && root == s1; c0 += kCmThreads) {
+            const int t = c0 + tid;
+            const unsigned long long key =
+                (t < s1 && rlabel[4 * t + 3] == -1) ? (unsigned long long)t : ~0ull;
+            const unsigned long long m = block_min_u64(key, lds.minv);
+            if (m != ~0ull)
+                root = (int)m;
         }
+        if (root >= s1)  // block-uniform; cannot happen while next < s1
+            break;
+        scan_from = root;
+
+        int32_t *best = permA, *trial = permB;
+        PassResult rr = cm_pass(rec, root, next, best, lds);
+        ++npass;
+        for (;;) {
+            // Clear the component's labels before relabelling it: the first
+            // component of a segment by a sweep over the whole segment (only
+            // it and unreached cells live there), later ones cell by cell.
+            if (next == s0) {
+                for (int v = s0 + tid; v < s1; v += kCmThreads)
+                    rlabel[4 * v + 3] = -1;
+            } else {
+                for (int l = next + tid; l < next + rr.count; l += kCmThreads)
+                    rlabel[4 * best[l] + 3] = -1;
+            }
+            __threadfence_block();
+            __syncthreads();
+            const PassResult rx = cm_pass(rec, rr.pick, next, trial, lds);
+            ++npass;
+            if (rx.ecc > rr.ecc) {
+                rr = rx;
+                int32_t *t = best;
+                best = trial;
+                trial = t;
+            } else {
+                break;
+            }
+        }
+        for (int l = next + tid; l < next + rr.count; l += kCmThreads)
+            perm[l] = best[l];
+        __threadfence_block();
+        __syncthreads();
+        next += rr.count;
     }
-    if (threadIdx.x == 0)
-        *out = n;
+    if (tid == 0)
+        passes[blockIdx.x] = npass;
+}
+
+__global__ void invert_kernel(int32_t n, const int32_t *__restrict__ perm,
+                              int32_t *__restrict__ label)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < n)
+        label[perm[l]] = l;
 }
 
 // rec[v] = (nb_0[v], nb_1[v], nb_2[v], -1): no cell labelled yet.
@@ -303,18 +383,6 @@ __global__ void build_records_kernel(int32_t n, int32_t ld, const int32_t *__res
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n)
         rec[v] = make_int4(nb[v], nb[ld + v], nb[2 * ld + v], -1);
-}
-
-__global__ void commit_labels_kernel(int32_t base, int32_t count, const int32_t *__restrict__ src,
-                                     int32_t *__restrict__ perm, int32_t *__restrict__ label)
-{
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < count) {
-        const int l = base + t;
-        const int v = src[l];
-        perm[l] = v;
-        label[v] = l;
-    }
 }
 
 __global__ void fill_kernel(int32_t *__restrict__ p, int32_t value, int64_t count)
@@ -341,29 +409,16 @@ hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *
     return hipGetLastError();
 }
 
-hipError_t launch_cm_component(int4 *rec, int32_t root, int32_t base, int32_t *perm,
-                               CmResult *res, hipStream_t s)
+hipError_t launch_cm_segments(int4 *rec, int32_t n, int32_t n_seg, const int64_t *seg,
+                              int32_t *permA, int32_t *permB, int32_t *perm, int32_t *label,
+                              int32_t *passes, hipStream_t s)
 {
-    hipLaunchKernelGGL(cm_component_kernel, dim3(1), dim3(kCmThreads), 0, s, rec, root, base,
-                       perm, res);
-    return hipGetLastError();
-}
-
-hipError_t launch_find_unlabelled(int32_t n, const int32_t *label, int32_t from, int32_t *out,
-                                  hipStream_t s)
-{
-    hipLaunchKernelGGL(find_unlabelled_kernel, dim3(1), dim3(kCmThreads), 0, s, n, label, from,
-                       out);
-    return hipGetLastError();
-}
-
-hipError_t launch_commit_labels(int32_t base, int32_t count, const int32_t *perm_src,
-                                int32_t *perm_dst, int32_t *label_dst, hipStream_t s)
-{
-    if (count <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(commit_labels_kernel, dim3((count + 255) / 256), dim3(256), 0, s, base,
-                       count, perm_src, perm_dst, label_dst);
+    hipLaunchKernelGGL(cm_segments_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, seg, permA,
+                       permB, perm, passes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(invert_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, label);
     return hipGetLastError();
 }
 

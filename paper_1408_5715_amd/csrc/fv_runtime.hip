@@ -40,6 +40,7 @@ fv_status fail(fv_status code, const char *fmt, ...)
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxCells = (int64_t(1) << 31) - 4096;
+constexpr int32_t kMaxSegments = 1 << 16;
 
 size_t align_up(size_t x)
 {
@@ -53,7 +54,7 @@ int64_t leading_dim(int64_t n)
 
 // Byte sizes of the arena regions for n cells (leading dimension ld).
 struct Layout {
-    size_t U, nb, nb16, nrm, area, idx, scratch, small, total;
+    size_t U, nb, nb16, nrm, area, idx, scratch, seg, small, total;
     explicit Layout(int64_t n)
     {
         const size_t ld = (size_t)leading_dim(n);
@@ -63,9 +64,12 @@ struct Layout {
         nrm = align_up(ld * 6 * 8);
         area = align_up(ld * 8);
         idx = align_up(ld * 4);
-        scratch = align_up(ld * 48);  // >= AoS normals (48 B), state (32 B), 4 CM arrays (16 B)
+        scratch = align_up(ld * 48);  // >= AoS normals (48 B), state (32 B), CM records + orders (24 B)
+        // segment offsets (int64), per-segment dt (double), per-segment pass counts (int32)
+        seg = align_up((size_t)(kMaxSegments + 1) * 8) + align_up((size_t)kMaxSegments * 8) +
+              align_up((size_t)kMaxSegments * 4);
         small = kAlign;
-        total = 2 * U + 2 * nb + nb16 + 2 * nrm + 2 * area + 2 * idx + scratch + small;
+        total = 2 * U + 2 * nb + nb16 + 2 * nrm + 3 * area + 2 * idx + scratch + seg + small;
     }
 };
 
@@ -88,10 +92,26 @@ struct fv_ctx {
     short4 *nb16_w = nullptr; // ... as 16-bit offsets, valid when `narrow`
     double *nrm_w = nullptr;
     double *inv_area_w = nullptr;
+    double *coef = nullptr;    // dt / V_T per working cell, for coef_dt
     int32_t *perm = nullptr;   // perm[new] = uploaded id
     int32_t *label = nullptr;  // label[uploaded id] = new
     char *scratch = nullptr;
-    char *small = nullptr;     // CmResult and flags
+    char *small = nullptr;     // flags
+    int64_t *seg_dev = nullptr;   // segment offsets (n_seg + 1)
+    double *dt_dev = nullptr;     // per-segment dt of `coef`
+    int32_t *passes_dev = nullptr;
+
+    int32_t n_seg = 1;
+    std::vector<int64_t> seg_host;  // segment offsets; a segment is an independent mesh
+    std::vector<double> coef_dt;    // dt per segment that `coef` holds (empty: stale)
+
+    int block = 256;  // step launch: workgroup size
+    int grid = 0;     // 0 = one workgroup per tile, else persistent workgroups
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;  // private stream for graph capture
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    long long graph_key[6] = {-1, -1, -1, -1, -1, -1};
 
     bool mesh_ready = false;
     bool state_ready = false;
@@ -186,63 +206,100 @@ fv_status regather_geometry(fv_ctx *c)
     HIP_TRY(hipMemcpyAsync(&too_far, dflag, sizeof(too_far), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->narrow = too_far == 0;
+    c->coef_dt.clear();
     return FV_OK;
 }
 
-// Cuthill-McKee labelling of the uploaded graph into c->perm / c->label.
+// Cuthill-McKee labelling of every segment of the uploaded graph into
+// c->perm / c->label, one workgroup per segment, all on the device.
 // Scratch use (bytes per cell): records 16, two candidate orders 4 + 4.
 fv_status cm_order(fv_ctx *c)
 {
     const int32_t n = c->n;
     const size_t ld = (size_t)c->ld;
     int4 *rec = reinterpret_cast<int4 *>(c->scratch);
-    int32_t *permA = reinterpret_cast<int32_t *>(rec + ld);  // best order so far
-    int32_t *permB = permA + ld;                             // trial order
-    fvk::CmResult *dres = reinterpret_cast<fvk::CmResult *>(c->small);
-    int32_t *dfind = reinterpret_cast<int32_t *>(c->small + 64);
+    int32_t *permA = reinterpret_cast<int32_t *>(rec + ld);
+    int32_t *permB = permA + ld;
+    HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
+    HIP_TRY(fvk::launch_cm_segments(rec, n, c->n_seg, c->seg_dev, permA, permB, c->perm,
+                                    c->label, c->passes_dev, c->stream));
+    return FV_OK;
+}
 
-    // One level structure (and its labelling) from `root`.
-    auto pass = [&](int32_t root, int32_t base, int32_t *perm, fvk::CmResult *out) -> fv_status {
-        HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
-        HIP_TRY(fvk::launch_cm_component(rec, root, base, perm, dres, c->stream));
-        HIP_TRY(hipMemcpyAsync(out, dres, sizeof(*out), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
+// Make c->coef hold dt[s] / V for every cell (no work if it already does).
+fv_status ensure_coef(fv_ctx *c, const double *dt)
+{
+    bool same = (int32_t)c->coef_dt.size() == c->n_seg;
+    for (int32_t k = 0; same && k < c->n_seg; ++k)
+        same = c->coef_dt[k] == dt[k];
+    if (same)
         return FV_OK;
-    };
+    HIP_TRY(hipMemcpyAsync(c->dt_dev, dt, (size_t)c->n_seg * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(fvk::launch_coef(c->n, c->n_seg, c->seg_dev, c->dt_dev, c->inv_area_w, c->coef,
+                             c->stream));
+    // the host array of dt values is read by the copy; keep it alive until then
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->coef_dt.assign(dt, dt + c->n_seg);
+    return FV_OK;
+}
 
-    HIP_TRY(fvk::launch_fill_i32(c->label, -1, n, c->stream));
-    int32_t next = 0;
-    int32_t scan_from = 0;
-    while (next < n) {
-        int32_t s = 0;
-        if (next > 0) {
-            HIP_TRY(fvk::launch_find_unlabelled(n, c->label, scan_from, dfind, c->stream));
-            HIP_TRY(hipMemcpyAsync(&s, dfind, sizeof(s), hipMemcpyDeviceToHost, c->stream));
-            HIP_TRY(hipStreamSynchronize(c->stream));
-            if (s >= n)
-                return fail(FV_EHIP, "renumbering lost track of unlabelled cells");
-        }
-        scan_from = s;
+void drop_graph(fv_ctx *c)
+{
+    if (c->graph_exec)
+        (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph)
+        (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    for (auto &k : c->graph_key)
+        k = -1;
+}
 
-        fvk::CmResult rr, rx;
-        if (fv_status st = pass(s, next, permA, &rr))
-            return st;
-        // George-Liu: move the root to the far end while the eccentricity grows
-        for (;;) {
-            if (fv_status st = pass(rr.pick, next, permB, &rx))
-                return st;
-            if (rx.ecc > rr.ecc) {
-                rr = rx;
-                std::swap(permA, permB);
-            } else {
-                break;
-            }
+// n_steps launches of the step, ping-ponging the state buffers; through a
+// captured graph (one launch of the whole sequence) when enabled.
+fv_status run_steps(fv_ctx *c, int32_t n_steps)
+{
+    if (n_steps == 0)
+        return FV_OK;
+    if (!c->use_graph) {
+        for (int32_t s = 0; s < n_steps; ++s) {
+            HIP_TRY(fvk::launch_step(c->n, c->ld, c->U[c->cur], c->U[c->cur ^ 1], c->nb_w,
+                                     c->nb16_w, c->nrm_w, c->coef, c->gamma, c->narrow, c->closed,
+                                     c->block, c->grid, c->stream));
+            c->cur ^= 1;
         }
-        if (rr.count <= 0 || next + (int64_t)rr.count > n)
-            return fail(FV_EHIP, "renumbering produced an inconsistent component size");
-        HIP_TRY(fvk::launch_commit_labels(next, rr.count, permA, c->perm, c->label, c->stream));
-        next += rr.count;
+        return FV_OK;
     }
+    const long long key[6] = {n_steps, c->cur, c->block, c->grid, c->narrow, c->closed};
+    bool hit = c->graph_exec != nullptr;
+    for (int k = 0; hit && k < 6; ++k)
+        hit = key[k] == c->graph_key[k];
+    if (!hit) {
+        drop_graph(c);
+        if (!c->cap_stream)
+            HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        int cur = c->cur;
+        hipError_t err = hipSuccess;
+        for (int32_t s = 0; s < n_steps && err == hipSuccess; ++s) {
+            err = fvk::launch_step(c->n, c->ld, c->U[cur], c->U[cur ^ 1], c->nb_w, c->nb16_w,
+                                   c->nrm_w, c->coef, c->gamma, c->narrow, c->closed, c->block,
+                                   c->grid, c->cap_stream);
+            cur ^= 1;
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t end = hipStreamEndCapture(c->cap_stream, &g);
+        if (err != hipSuccess)
+            return fail(FV_EHIP, "step launch during capture failed: %s", hipGetErrorString(err));
+        HIP_TRY(end);
+        c->graph = g;
+        HIP_TRY(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+        for (int k = 0; k < 6; ++k)
+            c->graph_key[k] = key[k];
+    }
+    HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+    c->cur ^= (n_steps & 1);
     return FV_OK;
 }
 
@@ -305,35 +362,71 @@ fv_status fv_create(int64_t n_cells, double gamma, void *d_arena, size_t arena_b
     p += lay.area;
     c->inv_area_w = reinterpret_cast<double *>(p);
     p += lay.area;
+    c->coef = reinterpret_cast<double *>(p);
+    p += lay.area;
     c->perm = reinterpret_cast<int32_t *>(p);
     p += lay.idx;
     c->label = reinterpret_cast<int32_t *>(p);
     p += lay.idx;
     c->scratch = p;
     p += lay.scratch;
+    c->seg_dev = reinterpret_cast<int64_t *>(p);
+    p += align_up((size_t)(kMaxSegments + 1) * 8);
+    c->dt_dev = reinterpret_cast<double *>(p);
+    p += align_up((size_t)kMaxSegments * 8);
+    c->passes_dev = reinterpret_cast<int32_t *>(p);
+    p += align_up((size_t)kMaxSegments * 4);
     c->small = p;
     *out = c;
     return FV_OK;
 }
 
-fv_status fv_upload_mesh(fv_ctx *c, const int32_t *nbr, const double *nrm, const double *area)
+}  // extern "C"
+
+namespace {
+
+// Segments: n_seg + 1 offsets from 0 to n, strictly increasing, and no face
+// crossing from one segment to another.
+fv_status validate_segments(int64_t n, int32_t n_seg, const int64_t *seg, const int32_t *nbr)
 {
-    g_last_error.clear();
-    if (fv_status st = check_ctx(c))
-        return st;
-    if (!nbr || !nrm || !area)
-        return fail(FV_EINVAL, "null mesh array");
+    if (n_seg < 1 || n_seg > kMaxSegments)
+        return fail(FV_EINVAL, "n_seg %d outside [1, %d]", n_seg, kMaxSegments);
+    if (seg[0] != 0 || seg[n_seg] != n)
+        return fail(FV_EINVAL, "segment offsets must run from 0 to n_cells");
+    for (int32_t k = 0; k < n_seg; ++k) {
+        if (seg[k + 1] <= seg[k])
+            return fail(FV_EINVAL, "segment %d is empty or offsets decrease", k);
+        for (int64_t i = seg[k]; i < seg[k + 1]; ++i)
+            for (int f = 0; f < 3; ++f) {
+                const int64_t j = nbr[3 * i + f];
+                if (j < seg[k] || j >= seg[k + 1])
+                    return fail(FV_EMESH, "cell %lld face %d: neighbour %lld lies in another segment",
+                                (long long)i, f, (long long)j);
+            }
+    }
+    return FV_OK;
+}
+
+fv_status upload(fv_ctx *c, int32_t n_seg, const int64_t *seg, const int32_t *nbr,
+                 const double *nrm, const double *area)
+{
     if (fv_status st = validate_mesh(c->n, nbr, nrm, area))
+        return st;
+    if (fv_status st = validate_segments(c->n, n_seg, seg, nbr))
         return st;
     const size_t n = (size_t)c->n;
     c->mesh_ready = false;
     c->state_ready = false;
+    drop_graph(c);
     c->closed = normals_closed(c->n, nrm);
+    c->n_seg = n_seg;
+    c->seg_host.assign(seg, seg + n_seg + 1);
+    HIP_TRY(hipMemcpyAsync(c->seg_dev, c->seg_host.data(), (n_seg + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->scratch, nbr, n * 3 * sizeof(int32_t), hipMemcpyHostToDevice,
                            c->stream));
     HIP_TRY(fvk::launch_nb_aos_to_soa(c->n, c->ld, reinterpret_cast<int32_t *>(c->scratch),
                                       c->nb_o, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));  // scratch is reused below
     HIP_TRY(hipMemcpyAsync(c->scratch, nrm, n * 6 * sizeof(double), hipMemcpyHostToDevice,
                            c->stream));
     HIP_TRY(fvk::launch_nrm_aos_to_soa(c->n, c->ld, reinterpret_cast<double *>(c->scratch),
@@ -347,6 +440,32 @@ fv_status fv_upload_mesh(fv_ctx *c, const int32_t *nbr, const double *nrm, const
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->mesh_ready = true;
     return FV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fv_status fv_upload_mesh(fv_ctx *c, const int32_t *nbr, const double *nrm, const double *area)
+{
+    g_last_error.clear();
+    if (fv_status st = check_ctx(c))
+        return st;
+    if (!nbr || !nrm || !area)
+        return fail(FV_EINVAL, "null mesh array");
+    const int64_t seg[2] = {0, c->n};
+    return upload(c, 1, seg, nbr, nrm, area);
+}
+
+fv_status fv_upload_batch(fv_ctx *c, int32_t n_meshes, const int64_t *mesh_begin,
+                          const int32_t *nbr, const double *nrm, const double *area)
+{
+    g_last_error.clear();
+    if (fv_status st = check_ctx(c))
+        return st;
+    if (!mesh_begin || !nbr || !nrm || !area)
+        return fail(FV_EINVAL, "null batch array");
+    return upload(c, n_meshes, mesh_begin, nbr, nrm, area);
 }
 
 fv_status fv_upload_state(fv_ctx *c, const double *U)
@@ -429,12 +548,60 @@ fv_status fv_step(fv_ctx *c, int32_t n_steps, double dt)
         return fail(FV_EINVAL, "dt %g must be finite and > 0", dt);
     if (!c->mesh_ready || !c->state_ready)
         return fail(FV_ESTATE, "upload the mesh and the state before stepping");
-    for (int32_t s = 0; s < n_steps; ++s) {
-        HIP_TRY(fvk::launch_step(c->n, c->ld, c->U[c->cur], c->U[c->cur ^ 1], c->nb_w, c->nb16_w,
-                                 c->nrm_w, c->inv_area_w, dt, c->gamma, c->narrow, c->closed,
-                                 c->stream));
-        c->cur ^= 1;
-    }
+    std::vector<double> dts((size_t)c->n_seg, dt);
+    if (fv_status st = ensure_coef(c, dts.data()))
+        return st;
+    return run_steps(c, n_steps);
+}
+
+fv_status fv_step_batch(fv_ctx *c, int32_t n_steps, const double *dt)
+{
+    g_last_error.clear();
+    if (fv_status st = check_ctx(c))
+        return st;
+    if (n_steps < 0)
+        return fail(FV_EINVAL, "n_steps %d < 0", n_steps);
+    if (!dt)
+        return fail(FV_EINVAL, "null dt array");
+    if (!c->mesh_ready || !c->state_ready)
+        return fail(FV_ESTATE, "upload the mesh and the state before stepping");
+    for (int32_t k = 0; k < c->n_seg; ++k)
+        if (!(std::isfinite(dt[k]) && dt[k] > 0.0))
+            return fail(FV_EINVAL, "dt[%d] = %g must be finite and > 0", k, dt[k]);
+    if (fv_status st = ensure_coef(c, dt))
+        return st;
+    return run_steps(c, n_steps);
+}
+
+fv_status fv_set_launch(fv_ctx *c, int32_t block, int32_t grid, int32_t use_graph)
+{
+    g_last_error.clear();
+    if (fv_status st = check_ctx(c))
+        return st;
+    if (block != 128 && block != 256 && block != 512)
+        return fail(FV_EINVAL, "block %d must be 128, 256 or 512", block);
+    if (grid < 0)
+        return fail(FV_EINVAL, "grid %d < 0", grid);
+    if (use_graph != 0 && use_graph != 1)
+        return fail(FV_EINVAL, "use_graph must be 0 or 1");
+    c->block = block;
+    c->grid = grid;
+    c->use_graph = use_graph == 1;
+    return FV_OK;
+}
+
+fv_status fv_renumber_passes(fv_ctx *c, int32_t *passes)
+{
+    g_last_error.clear();
+    if (fv_status st = check_ctx(c))
+        return st;
+    if (!passes)
+        return fail(FV_EINVAL, "null passes array");
+    if (!c->mesh_ready)
+        return fail(FV_ESTATE, "upload the mesh first");
+    HIP_TRY(hipMemcpyAsync(passes, c->passes_dev, (size_t)c->n_seg * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     return FV_OK;
 }
 
@@ -501,6 +668,9 @@ fv_status fv_destroy(fv_ctx *c)
     g_last_error.clear();
     if (!c)
         return fail(FV_EINVAL, "null context");
+    drop_graph(c);
+    if (c->cap_stream)
+        (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return FV_OK;
 }

@@ -29,7 +29,10 @@
 //   - kClosed: the third normal read as -(n_0 + n_1) instead of from memory;
 //     used when every cell's stored normals satisfy n_2 == -(n_0 + n_1)
 //     exactly, so the value is bit-identical to the stored one.
-// Bytes per cell update: 132 (general), 112 with both.
+// Bytes per cell update: 132 (general), 112 with both.  The cell's
+// dt / V_T comes from a per-cell array (formed as dt * (1 / V_T), the same
+// single rounding whatever the batch), so meshes of a batch can step with
+// their own dt in one launch.
 
 #include "fv_internal.h"
 
@@ -92,17 +95,15 @@ __device__ __forceinline__ Prim primitives(const double4 &U, double gamma)
     return q;
 }
 
+// Update of one cell i (the body of the step).
 template <bool kNarrow, bool kClosed>
-__global__ __launch_bounds__(kStepBlock) void fv_step_kernel(
-    int32_t n, int32_t ld, const double4 *__restrict__ U, double4 *__restrict__ Un,
-    const int32_t *__restrict__ nb, const short4 *__restrict__ nb16,
-    const double *__restrict__ nrm, const double *__restrict__ inv_area, double dt, double gamma)
+__device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__restrict__ U,
+                                            double4 *__restrict__ Un,
+                                            const int32_t *__restrict__ nb,
+                                            const short4 *__restrict__ nb16,
+                                            const double *__restrict__ nrm,
+                                            const double *__restrict__ coef, double gamma)
 {
-    const int blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
-    const int i = blk * kStepBlock + threadIdx.x;
-    if (i >= n)
-        return;
-
     int js[3];
     if constexpr (kNarrow) {
         const short4 o = nb16[i];
@@ -152,13 +153,87 @@ __global__ __launch_bounds__(kStepBlock) void fv_step_kernel(
         a3 += 0.5 * ((Ui.w + L.p) * VL + (Uj.w + R.p) * VR) - 0.5 * s * (Uj.w - Ui.w);
     }
 
-    const double k = dt * inv_area[i];
+    // coef = dt / V_T, formed as dt * (1 / V_T) by coef_kernel
+    const double k = coef[i];
     double4 out;
     out.x = Ui.x - k * a0;
     out.y = Ui.y - k * a1;
     out.z = Ui.z - k * a2;
     out.w = Ui.w - k * a3;
     Un[i] = out;
+}
+
+// Tiles of kBlock cells.  With one workgroup per tile the workgroup ids are
+// remapped so that each XCD takes one contiguous range of tiles; with a
+// persistent grid of fewer workgroups, the tiles are split into one
+// contiguous range per XCD and the workgroups of each XCD stride through it.
+template <int kBlock, bool kNarrow, bool kClosed>
+__global__ __launch_bounds__(kBlock) void fv_step_kernel(
+    int32_t n, int32_t ld, const double4 *__restrict__ U, double4 *__restrict__ Un,
+    const int32_t *__restrict__ nb, const short4 *__restrict__ nb16,
+    const double *__restrict__ nrm, const double *__restrict__ coef, double gamma)
+{
+    const int tiles = (n + kBlock - 1) / kBlock;
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G >= tiles) {
+        const int t = xcd_contiguous_block(b, G);
+        const int i = t * kBlock + threadIdx.x;
+        if (t < tiles && i < n)
+            update_cell<kNarrow, kClosed>(i, ld, U, Un, nb, nb16, nrm, coef, gamma);
+        return;
+    }
+    const int X = G < kXcds ? G : kXcds;  // XCDs that hold workgroups
+    const int x = b % X, k = b / X;
+    const int Px = (G - x + X - 1) / X;   // workgroups on XCD x
+    const int t0 = (int)((long long)tiles * x / X), t1 = (int)((long long)tiles * (x + 1) / X);
+    for (int t = t0 + k; t < t1; t += Px) {
+        const int i = t * kBlock + threadIdx.x;
+        if (i < n)
+            update_cell<kNarrow, kClosed>(i, ld, U, Un, nb, nb16, nrm, coef, gamma);
+    }
+}
+
+// coef[i] = dt[s] * inv_area[i] for the segment s holding i (seg: n_seg + 1
+// increasing offsets).
+__global__ void coef_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict__ seg,
+                            const double *__restrict__ dt, const double *__restrict__ inv_area,
+                            double *__restrict__ coef)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n)
+        return;
+    int lo = 0, hi = n_seg - 1;  // largest s with seg[s] <= i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    coef[i] = dt[lo] * inv_area[i];
+}
+
+template <int kBlock>
+hipError_t launch_step_block(int32_t n, int32_t ld, const double4 *U, double4 *Un,
+                             const int32_t *nb, const short4 *nb16, const double *nrm,
+                             const double *coef, double gamma, bool narrow, bool closed,
+                             int grid, hipStream_t s)
+{
+    const int tiles = (n + kBlock - 1) / kBlock;
+    const int G = (grid <= 0 || grid > tiles) ? tiles : grid;
+    if (narrow && closed)
+        hipLaunchKernelGGL((fv_step_kernel<kBlock, true, true>), dim3(G), dim3(kBlock), 0, s, n,
+                           ld, U, Un, nb, nb16, nrm, coef, gamma);
+    else if (narrow)
+        hipLaunchKernelGGL((fv_step_kernel<kBlock, true, false>), dim3(G), dim3(kBlock), 0, s,
+                           n, ld, U, Un, nb, nb16, nrm, coef, gamma);
+    else if (closed)
+        hipLaunchKernelGGL((fv_step_kernel<kBlock, false, true>), dim3(G), dim3(kBlock), 0, s,
+                           n, ld, U, Un, nb, nb16, nrm, coef, gamma);
+    else
+        hipLaunchKernelGGL((fv_step_kernel<kBlock, false, false>), dim3(G), dim3(kBlock), 0, s,
+                           n, ld, U, Un, nb, nb16, nrm, coef, gamma);
+    return hipGetLastError();
 }
 
 // 16-bit neighbour offsets of the working order; *too_far = 1 (every writer
@@ -180,24 +255,31 @@ __global__ void narrow_offsets_kernel(int32_t n, int32_t ld, const int32_t *__re
 }  // namespace
 
 hipError_t launch_step(int32_t n, int32_t ld, const double4 *U, double4 *Un, const int32_t *nb,
-                       const short4 *nb16, const double *nrm, const double *inv_area, double dt,
-                       double gamma, bool narrow, bool closed, hipStream_t s)
+                       const short4 *nb16, const double *nrm, const double *coef, double gamma,
+                       bool narrow, bool closed, int block, int grid, hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
-    const int blocks = (n + kStepBlock - 1) / kStepBlock;
-    if (narrow && closed)
-        hipLaunchKernelGGL((fv_step_kernel<true, true>), dim3(blocks), dim3(kStepBlock), 0, s, n,
-                           ld, U, Un, nb, nb16, nrm, inv_area, dt, gamma);
-    else if (narrow)
-        hipLaunchKernelGGL((fv_step_kernel<true, false>), dim3(blocks), dim3(kStepBlock), 0, s, n,
-                           ld, U, Un, nb, nb16, nrm, inv_area, dt, gamma);
-    else if (closed)
-        hipLaunchKernelGGL((fv_step_kernel<false, true>), dim3(blocks), dim3(kStepBlock), 0, s, n,
-                           ld, U, Un, nb, nb16, nrm, inv_area, dt, gamma);
-    else
-        hipLaunchKernelGGL((fv_step_kernel<false, false>), dim3(blocks), dim3(kStepBlock), 0, s, n,
-                           ld, U, Un, nb, nb16, nrm, inv_area, dt, gamma);
+    switch (block) {
+    case 128:
+        return launch_step_block<128>(n, ld, U, Un, nb, nb16, nrm, coef, gamma, narrow, closed,
+                                      grid, s);
+    case 512:
+        return launch_step_block<512>(n, ld, U, Un, nb, nb16, nrm, coef, gamma, narrow, closed,
+                                      grid, s);
+    default:
+        return launch_step_block<256>(n, ld, U, Un, nb, nb16, nrm, coef, gamma, narrow, closed,
+                                      grid, s);
+    }
+}
+
+hipError_t launch_coef(int32_t n, int32_t n_seg, const int64_t *seg, const double *dt,
+                       const double *inv_area, double *coef, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(coef_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, n_seg, seg, dt,
+                       inv_area, coef);
     return hipGetLastError();
 }
 

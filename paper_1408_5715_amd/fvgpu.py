@@ -27,9 +27,10 @@ FV_ORDER_CM = 1
 
 # every symbol include/fvgpu.h declares
 EXPORTS = (
-    "fv_arena_bytes", "fv_create", "fv_upload_mesh", "fv_upload_state", "fv_upload_state_device",
-    "fv_renumber", "fv_step", "fv_download_state", "fv_download_state_device",
-    "fv_bytes_per_update", "fv_check_state", "fv_destroy", "fv_last_error",
+    "fv_arena_bytes", "fv_create", "fv_upload_mesh", "fv_upload_batch", "fv_upload_state",
+    "fv_upload_state_device", "fv_renumber", "fv_step", "fv_step_batch", "fv_set_launch",
+    "fv_renumber_passes", "fv_download_state", "fv_download_state_device", "fv_bytes_per_update",
+    "fv_check_state", "fv_destroy", "fv_last_error",
 )
 
 
@@ -56,6 +57,10 @@ def lib() -> ctypes.CDLL:
         L.fv_arena_bytes.restype = sz
         L.fv_create.argtypes = [i64, dbl, vp, sz, vp, ctypes.POINTER(vp)]
         L.fv_upload_mesh.argtypes = [vp, vp, vp, vp]
+        L.fv_upload_batch.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.fv_step_batch.argtypes = [vp, i32, vp]
+        L.fv_set_launch.argtypes = [vp, i32, i32, i32]
+        L.fv_renumber_passes.argtypes = [vp, vp]
         L.fv_upload_state.argtypes = [vp, vp]
         L.fv_upload_state_device.argtypes = [vp, vp]
         L.fv_renumber.argtypes = [vp, i32, vp]
@@ -111,6 +116,30 @@ def fv_upload_mesh(ctx: int, nbr: np.ndarray, nrm: np.ndarray, area: np.ndarray)
     _check(lib().fv_upload_mesh(ctx, _ptr(nbr), _ptr(nrm), _ptr(area)))
 
 
+def fv_upload_batch(ctx: int, mesh_begin, nbr: np.ndarray, nrm: np.ndarray,
+                    area: np.ndarray) -> None:
+    mb = np.ascontiguousarray(mesh_begin, dtype=np.int64)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    nrm = np.ascontiguousarray(nrm, dtype=np.float64)
+    area = np.ascontiguousarray(area, dtype=np.float64)
+    _check(lib().fv_upload_batch(ctx, int(mb.size - 1), _ptr(mb), _ptr(nbr), _ptr(nrm), _ptr(area)))
+
+
+def fv_step_batch(ctx: int, n_steps: int, dt) -> None:
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    _check(lib().fv_step_batch(ctx, int(n_steps), _ptr(dt)))
+
+
+def fv_set_launch(ctx: int, block: int = 256, grid: int = 0, use_graph: bool = False) -> None:
+    _check(lib().fv_set_launch(ctx, int(block), int(grid), int(bool(use_graph))))
+
+
+def fv_renumber_passes(ctx: int, n_meshes: int) -> np.ndarray:
+    out = np.empty(n_meshes, dtype=np.int32)
+    _check(lib().fv_renumber_passes(ctx, _ptr(out)))
+    return out
+
+
 def fv_upload_state(ctx: int, U: np.ndarray) -> None:
     U = np.ascontiguousarray(U, dtype=np.float64)
     _check(lib().fv_upload_state(ctx, _ptr(U)))
@@ -158,7 +187,9 @@ def fv_last_error() -> str:
 class Solver:
     """One mesh on one GPU: arena from torch, work on torch's current stream."""
 
-    def __init__(self, nbr, nrm, area, gamma: float = 1.4, device="cuda:0", stream=None):
+    def __init__(self, nbr, nrm, area, gamma: float = 1.4, device="cuda:0", stream=None,
+                 mesh_begin=None):
+        """mesh_begin (optional): offsets of the independent meshes of a batch."""
         import torch
 
         self.torch = torch
@@ -170,7 +201,12 @@ class Solver:
         self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = fv_create(self.n, gamma, self.arena, self.nbytes, self.stream.cuda_stream)
-        fv_upload_mesh(self.ctx, nbr, nrm, area)
+        if mesh_begin is None:
+            self.n_meshes = 1
+            fv_upload_mesh(self.ctx, nbr, nrm, area)
+        else:
+            self.n_meshes = len(mesh_begin) - 1
+            fv_upload_batch(self.ctx, mesh_begin, nbr, nrm, area)
 
     def upload_state(self, U) -> None:
         if isinstance(U, np.ndarray):
@@ -183,8 +219,18 @@ class Solver:
         fv_renumber(self.ctx, method, perm)
         return perm
 
-    def step(self, n_steps: int, dt: float) -> None:
-        fv_step(self.ctx, n_steps, dt)
+    def step(self, n_steps: int, dt) -> None:
+        """dt: one value, or one per mesh of a batch."""
+        if np.ndim(dt) == 0:
+            fv_step(self.ctx, n_steps, float(dt))
+        else:
+            fv_step_batch(self.ctx, n_steps, dt)
+
+    def set_launch(self, block: int = 256, grid: int = 0, use_graph: bool = False) -> None:
+        fv_set_launch(self.ctx, block, grid, use_graph)
+
+    def renumber_passes(self) -> np.ndarray:
+        return fv_renumber_passes(self.ctx, self.n_meshes)
 
     def download(self) -> np.ndarray:
         U = np.empty((self.n, 4), dtype=np.float64)

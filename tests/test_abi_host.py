@@ -36,8 +36,11 @@ def test_arena_bytes():
     assert fv.fv_arena_bytes(-5) == 0
     assert fv.fv_arena_bytes(1 << 31) == 0
     b = fv.fv_arena_bytes(8192)
-    assert 240 * 8192 <= b <= 300 * 8192
+    fixed = 2 << 20  # the per-mesh tables of a batch (up to 65536 meshes)
+    assert 240 * 8192 <= b <= 300 * 8192 + fixed
     assert fv.fv_arena_bytes(8193) >= b
+    big = fv.fv_arena_bytes(1 << 21)
+    assert 250 * (1 << 21) <= big <= 280 * (1 << 21)
 
 
 def make_ctx(n):
@@ -141,3 +144,29 @@ def test_last_error_is_per_thread():
     t.join()
     assert seen["msg"] == ""
     assert fv.fv_last_error() != ""
+
+
+def test_batch_validation():
+    from fvgen.mesh import periodic_mesh
+
+    a, b = periodic_mesh(4), periodic_mesh(5)
+    n = a.n + b.n
+    nbr = np.concatenate([a.nbr, b.nbr + a.n])
+    nrm = np.concatenate([a.nrm, b.nrm])
+    area = np.concatenate([a.area, b.area])
+    ctx = make_ctx(n)
+    try:
+        for bad in ([0, a.n], [1, a.n, n], [0, a.n, n - 1], [0, a.n, a.n, n], [0, n + 1]):
+            expect(fv.FV_EINVAL, fv.fv_upload_batch, ctx, bad, nbr, nrm, area)
+        # one mesh split across two segments: faces cross the boundary
+        assert "another segment" in expect(fv.FV_EMESH, fv.fv_upload_batch, ctx,
+                                          [0, a.n // 2, n], nbr, nrm, area)
+        expect(fv.FV_EINVAL, fv.fv_set_launch, ctx, 64, 0, False)
+        expect(fv.FV_EINVAL, fv.fv_set_launch, ctx, 256, -1, False)
+        assert fv.lib().fv_set_launch(ctx, 256, 0, 2) == fv.FV_EINVAL
+        fv.fv_set_launch(ctx, 512, 1024, True)
+        expect(fv.FV_ESTATE, fv.fv_step_batch, ctx, 1, np.ones(2))
+        assert fv.lib().fv_step_batch(ctx, 1, None) == fv.FV_EINVAL
+        expect(fv.FV_ESTATE, fv.fv_renumber_passes, ctx, 2)
+    finally:
+        fv.fv_destroy(ctx)
