@@ -34,6 +34,8 @@ class Oracle:
         L.oracle_step.restype = ctypes.c_int
         L.oracle_cm_order.argtypes = [i64, vp, vp]
         L.oracle_cm_order.restype = ctypes.c_int
+        L.oracle_am1_order.argtypes = [i64, vp, vp]
+        L.oracle_am1_order.restype = ctypes.c_int
         L.oracle_bandwidth.argtypes = [i64, vp, vp, vp]
         L.oracle_bandwidth.restype = ctypes.c_int
         self.lib = L
@@ -78,6 +80,14 @@ class Oracle:
             raise RuntimeError("oracle_cm_order failed")
         return perm
 
+    def am1_order(self, nbr) -> np.ndarray:
+        """Amoeba1 permutation (section 4.2), new label -> old id."""
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        perm = np.empty(nbr.shape[0], dtype=np.int32)
+        if self.lib.oracle_am1_order(nbr.shape[0], _p(nbr), _p(perm)) != 0:
+            raise RuntimeError("oracle_am1_order failed")
+        return perm
+
     def bandwidth(self, nbr, label) -> dict:
         """B_f(G), C_BW and S_BW of the labelling label[old id] = new label."""
         nbr = np.ascontiguousarray(nbr, dtype=np.int32)
@@ -114,6 +124,10 @@ def step(*a, **k):
 
 def cm_order(*a, **k):
     return default().cm_order(*a, **k)
+
+
+def am1_order(*a, **k):
+    return default().am1_order(*a, **k)
 
 
 def bandwidth(*a, **k):

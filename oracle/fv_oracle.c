@@ -24,7 +24,9 @@
  *     serial bandwidth S_BW.
  *   - Section 4.2.2: the pseudo-diameter start vertex used before the
  *     breadth-first labelling (Gibbs-Poole-Stockmeyer subroutine, realised
- *     here as the George-Liu pseudo-peripheral node search).
+ *     here as the George-Liu pseudo-peripheral node search), and the Amoeba1
+ *     (AM1) labelling of section 4.2 (bookkeeping s(i), u(i), I, imp(i) of
+ *     section 4.2.1; candidate choice of section 4.2.2).
  *
  * Readings taken where the paper is silent or garbled:
  *   - Dissipation sign: F = (F_L + F_R)/2 - alpha (U_R - U_L)/2 as in
@@ -37,6 +39,11 @@
  *   - Faces are summed in stored order, ((F_0 + F_1) + F_2).
  *   - S_BW uses closed neighbourhoods (a node is a neighbour of itself).
  *   - Cuthill-McKee children are visited in order of (degree, id).
+ *   - AM1: the "random element of u(I)" that starts the candidate search is
+ *     the smallest id of u(I); candidates are scanned in increasing id; s(i)
+ *     of a part's first node is 0; AM1 starts from the same pseudo-peripheral
+ *     root as Cuthill-McKee, and a disconnected graph restarts a new part
+ *     from its lowest unlabelled id.
  */
 
 #include <math.h>
@@ -225,6 +232,30 @@ static int64_t level_structure(int64_t n, const int32_t *nbr, const uint8_t *mar
 }
 
 /*
+ * George-Liu pseudo-peripheral root of the component of s among unmarked
+ * vertices: from r = s, take the last level's vertex x of minimum
+ * (degree, id); if x has a larger eccentricity than r, continue from x,
+ * else return r.
+ */
+static int64_t pseudo_peripheral_root(int64_t n, const int32_t *nbr, const uint8_t *mark,
+                                      int64_t s, int64_t *queue, int64_t *dist)
+{
+    int64_t r = s, x;
+    int64_t ecc_r = level_structure(n, nbr, mark, r, queue, dist, &x);
+    for (;;) {
+        int64_t x2;
+        int64_t ecc_x = level_structure(n, nbr, mark, x, queue, dist, &x2);
+        if (ecc_x > ecc_r) {
+            r = x;
+            ecc_r = ecc_x;
+            x = x2;
+        } else {
+            return r;
+        }
+    }
+}
+
+/*
  * Cuthill-McKee ordering of the dual graph given by nbr [n][3].
  * perm_out[new_label] = old id.
  * Each connected component is labelled in turn, starting with the component
@@ -257,22 +288,7 @@ int oracle_cm_order(int64_t n, const int32_t *nbr, int32_t *perm_out)
     while (next < n) {
         while (mark[scan])
             ++scan;
-        int64_t r = scan;
-
-        /* pseudo-peripheral root */
-        int64_t x;
-        int64_t ecc_r = level_structure(n, nbr, mark, r, queue, dist, &x);
-        for (;;) {
-            int64_t x2;
-            int64_t ecc_x = level_structure(n, nbr, mark, x, queue, dist, &x2);
-            if (ecc_x > ecc_r) {
-                r = x;
-                ecc_r = ecc_x;
-                x = x2;
-            } else {
-                break;
-            }
-        }
+        const int64_t r = pseudo_peripheral_root(n, nbr, mark, scan, queue, dist);
 
         /* Cuthill-McKee labelling of the component from r */
         int64_t head = next;
@@ -369,5 +385,130 @@ int oracle_bandwidth(int64_t n, const int32_t *nbr, const int32_t *label, int64_
     out[2] = sbw;
     free(s);
     free(e);
+    return 0;
+}
+
+
+/*
+ * Amoeba1 (AM1) labelling of section 4.2, perm_out[new_label] = old id.
+ *
+ * A part P grows one node per step.  For the node at position i of P
+ * (0-based here; the paper counts from 1):
+ *   s(i)  = i - (smallest position among its neighbours in P), 0 if none
+ *           earlier;
+ *   u(i)  = its neighbours not yet in P;
+ *   I     = first position whose u() is not empty;
+ *   imp(i) = (|P| - 1 - i) + |u(i)| + s(i) for i >= I, 0 for i < I.
+ * Each step takes the candidates k of u(I); for each, local_max is the
+ * largest imp(l) over its neighbours l in P other than node(I); the first
+ * candidate whose local_max exceeds every earlier one (starting from 0) is
+ * appended, else the first candidate.  The part starts at the George-Liu
+ * pseudo-peripheral root (section 4.2.2's pseudo-diameter endpoint).
+ * Returns 0, or -1 on a bad argument or allocation failure.
+ */
+int oracle_am1_order(int64_t n, const int32_t *nbr, int32_t *perm_out)
+{
+    if (n <= 0 || !nbr || !perm_out)
+        return -1;
+    uint8_t *mark = (uint8_t *)calloc((size_t)n, 1);
+    int64_t *pos = (int64_t *)malloc((size_t)n * sizeof(int64_t));   /* position in P or -1 */
+    int64_t *sv = (int64_t *)malloc((size_t)n * sizeof(int64_t));    /* s() by position */
+    int64_t *uc = (int64_t *)malloc((size_t)n * sizeof(int64_t));    /* |u()| by position */
+    int64_t *queue = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *dist = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!mark || !pos || !sv || !uc || !queue || !dist) {
+        free(mark);
+        free(pos);
+        free(sv);
+        free(uc);
+        free(queue);
+        free(dist);
+        return -1;
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        pos[v] = -1;
+        dist[v] = -1;
+    }
+    int64_t size = 0; /* nodes labelled so far, over all parts */
+    int64_t scan = 0;
+    while (size < n) {
+        while (mark[scan])
+            ++scan;
+        /* pseudo-peripheral root of this component, as for Cuthill-McKee */
+        const int64_t r = pseudo_peripheral_root(n, nbr, mark, scan, queue, dist);
+        const int64_t first = size; /* positions of this part start here */
+        int64_t I = first;
+        int64_t next = r;
+        for (;;) {
+            /* append `next` at position size */
+            const int64_t m = size;
+            perm_out[m] = (int32_t)next;
+            pos[next] = m;
+            mark[next] = 1;
+            ++size;
+            int32_t nb[3];
+            const int d = distinct_neighbours(nbr, next, nb);
+            int64_t lo = m, free_count = 0;
+            for (int g = 0; g < d; ++g) {
+                const int64_t p = pos[nb[g]];
+                if (p >= 0) {
+                    if (p < lo)
+                        lo = p;
+                    uc[p] -= 1; /* next is no longer uncovered for nb[g] */
+                } else {
+                    ++free_count;
+                }
+            }
+            sv[m] = m - lo;
+            uc[m] = free_count;
+            while (I < size && uc[I] == 0)
+                ++I;
+            if (I >= size)
+                break; /* component complete */
+
+            /* candidates: u(I) in increasing id */
+            const int64_t vI = perm_out[I];
+            int32_t cnb[3];
+            const int cd = distinct_neighbours(nbr, vI, cnb);
+            int32_t cand[3] = {0, 0, 0};
+            int nc = 0;
+            for (int g = 0; g < cd; ++g)
+                if (pos[cnb[g]] < 0)
+                    cand[nc++] = cnb[g];
+            for (int a1 = 1; a1 < nc; ++a1)
+                for (int b1 = a1; b1 > 0 && cand[b1 - 1] > cand[b1]; --b1) {
+                    const int32_t t = cand[b1];
+                    cand[b1] = cand[b1 - 1];
+                    cand[b1 - 1] = t;
+                }
+            int64_t chosen = cand[0];
+            int64_t global_max = 0;
+            for (int c = 0; c < nc; ++c) {
+                int32_t knb[3];
+                const int kd = distinct_neighbours(nbr, cand[c], knb);
+                int64_t local_max = 0;
+                for (int g = 0; g < kd; ++g) {
+                    const int64_t p = pos[knb[g]];
+                    if (p < 0 || knb[g] == vI)
+                        continue;
+                    const int64_t imp = p < I ? 0 : (size - 1 - p) + uc[p] + sv[p];
+                    if (imp > local_max)
+                        local_max = imp;
+                }
+                if (local_max > global_max) {
+                    chosen = cand[c];
+                    global_max = local_max;
+                }
+            }
+            next = chosen;
+        }
+        (void)first;
+    }
+    free(mark);
+    free(pos);
+    free(sv);
+    free(uc);
+    free(queue);
+    free(dist);
     return 0;
 }

@@ -210,6 +210,16 @@ def pin_cm_golden(o):
     return True, "all cases"
 
 
+def pin_am1_golden(o):
+    d = _load("bandwidth_cases.json")
+    for c in d["cases"]:
+        if "am1_perm" in c:
+            got = o.am1_order(np.array(c["nbr"], dtype=np.int32)).tolist()
+            if got != c["am1_perm"]:
+                return False, f"{c['name']}: {got} != {c['am1_perm']}"
+    return True, "all cases"
+
+
 def pin_bandwidth_golden(o):
     d = _load("bandwidth_cases.json")
     for c in d["cases"]:
@@ -294,4 +304,5 @@ def pin_contact_advection(o, N=16, tf=1.0, u=0.6, v=0.8):
 
 
 QUICK_PINS = [pin_golden_faces, pin_consistency, pin_xy_form, pin_antisymmetry, pin_conservation,
-              pin_freestream, pin_translation, pin_stability, pin_contact_advection, pin_cm_golden, pin_bandwidth_golden]
+              pin_freestream, pin_translation, pin_stability, pin_contact_advection, pin_cm_golden,
+              pin_am1_golden, pin_bandwidth_golden]

@@ -38,6 +38,8 @@ MUTATIONS = {
     "S_BW from prefix minimum": ("if (s[i + 1] < s[i])\n            s[i] = s[i + 1];",
                                  "if (s[i + 1] > s[i])\n            s[i] = s[i + 1];"),
     "bandwidth not doubled": ("out[1] = 2 * B + 1;", "out[1] = B + 1;"),
+    "AM1 ties move the candidate": ("if (local_max > global_max) {", "if (local_max >= global_max) {"),
+    "AM1 scans from node(I) too": ("if (p < 0 || knb[g] == vI)", "if (p < 0)"),
 }
 
 

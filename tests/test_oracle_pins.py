@@ -107,3 +107,18 @@ def test_bad_arguments(o):
     m, U0, dt = pins.c1_like(4)
     with pytest.raises(RuntimeError):
         o.step(m.nbr, m.nrm, m.area, U0, dt, -1)
+
+
+def test_am1_order_is_valid(o):
+    """AM1 on a shuffled 32 x 32 mesh: a permutation in which every cell after
+    the first is adjacent to an earlier one (the part grows by neighbours),
+    with the band of the structured order."""
+    from fvgen.mesh import shuffled_periodic_mesh
+
+    m = shuffled_periodic_mesh(32)
+    perm = o.am1_order(m.nbr)
+    assert np.array_equal(np.sort(perm), np.arange(m.n))
+    lab = np.empty(m.n, dtype=np.int64)
+    lab[perm] = np.arange(m.n)
+    assert all(np.min(lab[m.nbr[v]]) < lab[v] for v in perm[1:])
+    assert o.bandwidth(m.nbr, lab)["B"] <= 3 * 32
