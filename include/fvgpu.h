@@ -152,6 +152,19 @@ fv_status fv_step(fv_ctx *ctx, int32_t n_steps, double dt);
 fv_status fv_step_batch(fv_ctx *ctx, int32_t n_steps, const double *dt);
 
 /*
+ * Adjoint of one step of size dt (section 6.2.2's update, differentiated):
+ * given the state U^n at which the step is taken and the cotangent lambda of
+ * U^{n+1}, overwrite lambda with the cotangent of U^n,
+ *   lambda_k <- lambda_k - sum_f (dG(U_k, U_j, n_f)/dU_k)^T (c_k lambda_k - c_j lambda_j)
+ * with G the face flux times |n_f| and c = dt / V.  For a batch, all meshes
+ * use this dt.
+ *   d_U       device double [n][4], numbering of the uploaded mesh, 32-byte aligned.
+ *   d_lambda  device double [n][4], same numbering, in/out, 32-byte aligned.
+ * Asynchronous on the stream; uses the context's scratch memory.
+ */
+fv_status fv_step_adjoint(fv_ctx *ctx, const double *d_U, double *d_lambda, double dt);
+
+/*
  * Launch shape of the step kernel (no effect on results, which are bitwise
  * independent of it).
  *   block      workgroup size: 128, 256 (default) or 512 cells.

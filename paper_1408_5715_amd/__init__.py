@@ -27,6 +27,7 @@ from .fvgpu import (  # noqa: F401
     fv_renumber,
     fv_renumber_passes,
     fv_set_launch,
+    fv_step_adjoint,
     fv_step_batch,
     fv_upload_batch,
     fv_step,

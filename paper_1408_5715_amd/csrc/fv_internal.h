@@ -36,6 +36,14 @@ hipError_t launch_coef(int32_t n, int32_t n_seg, const int64_t *seg, const doubl
 hipError_t launch_narrow_offsets(int32_t n, int32_t ld, const int32_t *nb, short4 *nb16,
                                  int32_t *too_far, hipStream_t s);
 
+// Cotangent of one step's input from the cotangent of its output, on arrays
+// in any one numbering (mesh arrays nb [3][ld], nrm [6][ld], area [ld]):
+// lam = lam_next - sum_f (dG(U_k, U_j, n_f)/dU_k)^T (c_k lam_next_k - c_j lam_next_j),
+// c = dt * (1 / area).  lam and lam_next must not overlap.
+hipError_t launch_adjoint(int32_t n, int32_t ld, const double4 *U, const double4 *lam_next,
+                          double4 *lam, const int32_t *nb, const double *nrm, const double *area,
+                          double dt, double gamma, hipStream_t s);
+
 // ---- renumbering --------------------------------------------------------
 // rec[v] = (nb_0[v], nb_1[v], nb_2[v], -1): the graph with an empty label slot.
 hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *rec,

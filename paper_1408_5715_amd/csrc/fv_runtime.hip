@@ -573,6 +573,28 @@ fv_status fv_step_batch(fv_ctx *c, int32_t n_steps, const double *dt)
     return run_steps(c, n_steps);
 }
 
+fv_status fv_step_adjoint(fv_ctx *c, const double *d_U, double *d_lambda, double dt)
+{
+    g_last_error.clear();
+    if (fv_status st = check_ctx(c))
+        return st;
+    if (!d_U || !d_lambda)
+        return fail(FV_EINVAL, "null device array");
+    if (reinterpret_cast<uintptr_t>(d_U) % 32 != 0 || reinterpret_cast<uintptr_t>(d_lambda) % 32 != 0)
+        return fail(FV_EINVAL, "device arrays must be 32-byte aligned");
+    if (!(std::isfinite(dt) && dt > 0.0))
+        return fail(FV_EINVAL, "dt %g must be finite and > 0", dt);
+    if (!c->mesh_ready)
+        return fail(FV_ESTATE, "upload the mesh first");
+    double4 *out = reinterpret_cast<double4 *>(c->scratch);
+    HIP_TRY(fvk::launch_adjoint(c->n, c->ld, reinterpret_cast<const double4 *>(d_U),
+                                reinterpret_cast<const double4 *>(d_lambda), out, c->nb_o,
+                                c->nrm_o, c->area_o, dt, c->gamma, c->stream));
+    HIP_TRY(hipMemcpyAsync(d_lambda, out, (size_t)c->n * sizeof(double4), hipMemcpyDeviceToDevice,
+                           c->stream));
+    return FV_OK;
+}
+
 fv_status fv_set_launch(fv_ctx *c, int32_t block, int32_t grid, int32_t use_graph)
 {
     g_last_error.clear();

@@ -28,7 +28,8 @@ FV_ORDER_CM = 1
 # every symbol include/fvgpu.h declares
 EXPORTS = (
     "fv_arena_bytes", "fv_create", "fv_upload_mesh", "fv_upload_batch", "fv_upload_state",
-    "fv_upload_state_device", "fv_renumber", "fv_step", "fv_step_batch", "fv_set_launch",
+    "fv_upload_state_device", "fv_renumber", "fv_step", "fv_step_batch", "fv_step_adjoint",
+    "fv_set_launch",
     "fv_renumber_passes", "fv_download_state", "fv_download_state_device", "fv_bytes_per_update",
     "fv_check_state", "fv_destroy", "fv_last_error",
 )
@@ -60,6 +61,7 @@ def lib() -> ctypes.CDLL:
         L.fv_upload_batch.argtypes = [vp, i32, vp, vp, vp, vp]
         L.fv_step_batch.argtypes = [vp, i32, vp]
         L.fv_set_launch.argtypes = [vp, i32, i32, i32]
+        L.fv_step_adjoint.argtypes = [vp, vp, vp, dbl]
         L.fv_renumber_passes.argtypes = [vp, vp]
         L.fv_upload_state.argtypes = [vp, vp]
         L.fv_upload_state_device.argtypes = [vp, vp]
@@ -128,6 +130,10 @@ def fv_upload_batch(ctx: int, mesh_begin, nbr: np.ndarray, nrm: np.ndarray,
 def fv_step_batch(ctx: int, n_steps: int, dt) -> None:
     dt = np.ascontiguousarray(dt, dtype=np.float64)
     _check(lib().fv_step_batch(ctx, int(n_steps), _ptr(dt)))
+
+
+def fv_step_adjoint(ctx: int, d_U, d_lambda, dt: float) -> None:
+    _check(lib().fv_step_adjoint(ctx, _ptr(d_U), _ptr(d_lambda), float(dt)))
 
 
 def fv_set_launch(ctx: int, block: int = 256, grid: int = 0, use_graph: bool = False) -> None:

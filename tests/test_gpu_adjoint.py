@@ -1,0 +1,94 @@
+"""The hand-written adjoint of the step (fv_step_adjoint) behind a
+torch.autograd.Function: gradients of a rollout against the PyTorch CPU
+reference (autograd through the paper's equations), against central finite
+differences of the GPU forward, and invariant to checkpoint spacing and cell
+order."""
+
+import numpy as np
+import pytest
+
+import paper_1408_5715_amd as fv
+from gpu_helpers import log, vortex_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def perturbed_case(N, seed=0):
+    m, U0, dt = vortex_case(N)
+    rng = np.random.default_rng(seed)
+    U0 = U0 * (1.0 + 0.02 * rng.standard_normal(U0.shape))
+    w = rng.standard_normal(U0.shape)
+    return m, U0, dt, w
+
+
+def gpu_grad(torch, m, U0, dt, w, steps, checkpoint=4, order=fv.FV_ORDER_IDENTITY):
+    from paper_1408_5715_amd.autograd import rollout
+
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        if order != fv.FV_ORDER_IDENTITY:
+            s.renumber(order)
+        x = torch.tensor(U0, dtype=torch.float64, device="cuda", requires_grad=True)
+        out = rollout(x, s, steps, dt, checkpoint)
+        loss = (out * torch.tensor(w, device="cuda")).sum()
+        loss.backward()
+        return x.grad.cpu().numpy(), float(loss)
+    finally:
+        s.close()
+
+
+def test_adjoint_matches_cpu_reference_gradient(torch):
+    from oracle import torch_ref
+
+    m, U0, dt, w = perturbed_case(6)
+    g, _ = gpu_grad(torch, m, U0, dt, w, steps=5, checkpoint=2)
+    x = torch.tensor(U0, dtype=torch.float64, requires_grad=True)
+    out = torch_ref.rollout(torch_ref.Mesh(m.nbr, m.nrm, m.area), x, dt, 5)
+    (out * torch.from_numpy(w)).sum().backward()
+    ref = x.grad.numpy()
+    err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    log(f"adjoint vs CPU autograd: relative max error {err:.2e}")
+    assert err <= 1e-10
+
+
+def test_adjoint_matches_finite_differences(torch):
+    from paper_1408_5715_amd.autograd import rollout
+
+    m, U0, dt, w = perturbed_case(12, seed=1)
+    steps = 8
+    g, _ = gpu_grad(torch, m, U0, dt, w, steps)
+    rng = np.random.default_rng(7)
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        def L(U):
+            with torch.no_grad():
+                out = rollout(torch.tensor(U, device="cuda"), s, steps, dt)
+            return float((out.cpu().numpy() * w).sum())
+
+        for trial in range(3):
+            e = rng.standard_normal(U0.shape) * np.abs(U0)
+            eps = 1e-6
+            fd = (L(U0 + eps * e) - L(U0 - eps * e)) / (2 * eps)
+            an = float((g * e).sum())
+            log(f"finite difference {fd:.12e} adjoint {an:.12e}")
+            assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9
+    finally:
+        s.close()
+
+
+def test_adjoint_checkpoint_and_order_invariance(torch):
+    m, U0, dt, w = perturbed_case(16, seed=2)
+    ref, _ = gpu_grad(torch, m, U0, dt, w, steps=20, checkpoint=1)
+    for cp in (3, 7, 20):
+        g, _ = gpu_grad(torch, m, U0, dt, w, steps=20, checkpoint=cp)
+        assert np.array_equal(g, ref), cp
+    g, _ = gpu_grad(torch, m, U0, dt, w, steps=20, checkpoint=4, order=fv.FV_ORDER_CM)
+    assert np.array_equal(g, ref)

@@ -122,3 +122,17 @@ def test_am1_order_is_valid(o):
     lab[perm] = np.arange(m.n)
     assert all(np.min(lab[m.nbr[v]]) < lab[v] for v in perm[1:])
     assert o.bandwidth(m.nbr, lab)["B"] <= 3 * 32
+
+
+def test_torch_reference_matches_oracle(o):
+    """The PyTorch CPU transcription of the step (used for reference
+    gradients) agrees with the C oracle to round-off."""
+    import torch
+
+    from oracle import torch_ref
+
+    m, U0, dt = pins.c1_like(8)
+    ref = o.step(m.nbr, m.nrm, m.area, U0, dt, 10)
+    got = torch_ref.rollout(torch_ref.Mesh(m.nbr, m.nrm, m.area), torch.from_numpy(U0), dt, 10)
+    err = np.max(np.abs(got.numpy() - ref), axis=0) / np.max(np.abs(ref), axis=0)
+    assert np.all(err <= 1e-14), err
