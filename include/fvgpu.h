@@ -50,6 +50,8 @@ typedef int32_t fv_status;
 #define FV_ORDER_IDENTITY 0
 #define FV_ORDER_CM 1
 
+#define FV_CORRECTION_PARAMS 5252
+
 /*
  * Device bytes the arena passed to fv_create must hold for n_cells cells
  * (about 256 bytes per cell).  Returns 0 if n_cells <= 0 or too large for
@@ -163,6 +165,28 @@ fv_status fv_step_batch(fv_ctx *ctx, int32_t n_steps, const double *dt);
  * Asynchronous on the stream; uses the context's scratch memory.
  */
 fv_status fv_step_adjoint(fv_ctx *ctx, const double *d_U, double *d_lambda, double dt);
+
+/*
+ * Learned correction of the face flux (not in the paper; added to its
+ * Lax-Friedrichs flux of section 6.2.2).  Per face, with e the unit normal,
+ * t = (-e_y, e_x), l the face length, a = 1/V and c = dt/V of both cells:
+ *   x(L, R, n) = [rho_L - 1, u.e_L, u.t_L, p_L - 1, rho_R - 1, u.e_R, u.t_R,
+ *                 p_R - 1, e_x, e_y, l^2 (a_L + a_R)/2, l (c_L + c_R)/2]
+ *   y(x) = W3^T h2 + b3, h2 = s(W2^T h1 + b2), h1 = s(W1^T x + b1),
+ *   s(z) = z / (1 + |z|), inputs, activations and weights in bfloat16,
+ *   products summed in float32;
+ *   G += l (R(e) y(x(L, R, n)) - R(-e) y(x(R, L, -n))),
+ *   R(e) y = (y0, y1 e_x + y2 t_x, y1 e_y + y2 t_y, y3).
+ * The added flux is exactly antisymmetric across every face, so mass,
+ * momentum and energy stay conserved to round-off.
+ *   params  host float [FV_CORRECTION_PARAMS]: W1 [12][64], b1 [64],
+ *           W2 [64][64], b2 [64], W3 [64][4], b3 [4], row-major [in][out];
+ *           NULL disables the correction (the plain step).
+ *   count   FV_CORRECTION_PARAMS, or 0 with NULL.
+ * FV_EINVAL on a wrong count or a non-finite parameter.  Applies to every
+ * later fv_step / fv_step_batch.  Synchronises the stream.
+ */
+fv_status fv_set_correction(fv_ctx *ctx, const float *params, int32_t count);
 
 /*
  * Launch shape of the step kernel (no effect on results, which are bitwise

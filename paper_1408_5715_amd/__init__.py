@@ -12,6 +12,7 @@ from .fvgpu import (  # noqa: F401
     FV_ENOMEM,
     FV_ESTATE,
     FV_OK,
+    FV_CORRECTION_PARAMS,
     FV_ORDER_CM,
     FV_ORDER_IDENTITY,
     FVError,
@@ -26,6 +27,7 @@ from .fvgpu import (  # noqa: F401
     fv_last_error,
     fv_renumber,
     fv_renumber_passes,
+    fv_set_correction,
     fv_set_launch,
     fv_step_adjoint,
     fv_step_batch,

@@ -44,6 +44,19 @@ hipError_t launch_adjoint(int32_t n, int32_t ld, const double4 *U, const double4
                           double4 *lam, const int32_t *nb, const double *nrm, const double *area,
                           double dt, double gamma, hipStream_t s);
 
+// Learned correction: the packed MLP (24 weight fragments of 64 lanes x 4
+// bfloat16 = kCorrFragShorts shorts, then 144 float biases) and the step
+// that adds it to the flux (see fv_learned.hip).
+constexpr int kCorrParams = 12 * 64 + 64 + 64 * 64 + 64 + 64 * 4 + 4;  // 5252
+constexpr int kCorrFragShorts = 24 * 64 * 4;
+constexpr int kCorrBias = 144;
+void pack_correction(const float *params, short *frags, float *bias);
+hipError_t launch_step_learned(int32_t n, int32_t ld, const double4 *U, double4 *Un,
+                               const int32_t *nb, const short4 *nb16, const double *nrm,
+                               const double *coef, const double *inv_area, const short *frags,
+                               const float *bias, double gamma, bool narrow, bool closed, int grid,
+                               hipStream_t s);
+
 // ---- renumbering --------------------------------------------------------
 // rec[v] = (nb_0[v], nb_1[v], nb_2[v], -1): the graph with an empty label slot.
 hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *rec,

@@ -54,7 +54,7 @@ int64_t leading_dim(int64_t n)
 
 // Byte sizes of the arena regions for n cells (leading dimension ld).
 struct Layout {
-    size_t U, nb, nb16, nrm, area, idx, scratch, seg, small, total;
+    size_t U, nb, nb16, nrm, area, idx, scratch, seg, corr, small, total;
     explicit Layout(int64_t n)
     {
         const size_t ld = (size_t)leading_dim(n);
@@ -68,8 +68,9 @@ struct Layout {
         // segment offsets (int64), per-segment dt (double), per-segment pass counts (int32)
         seg = align_up((size_t)(kMaxSegments + 1) * 8) + align_up((size_t)kMaxSegments * 8) +
               align_up((size_t)kMaxSegments * 4);
+        corr = align_up(fvk::kCorrFragShorts * 2) + align_up(fvk::kCorrBias * 4);
         small = kAlign;
-        total = 2 * U + 2 * nb + nb16 + 2 * nrm + 3 * area + 2 * idx + scratch + seg + small;
+        total = 2 * U + 2 * nb + nb16 + 2 * nrm + 3 * area + 2 * idx + scratch + seg + corr + small;
     }
 };
 
@@ -108,6 +109,9 @@ struct fv_ctx {
     int block = 256;  // step launch: workgroup size
     int grid = 0;     // 0 = one workgroup per tile, else persistent workgroups
     bool use_graph = false;
+    bool corr_on = false;           // learned flux correction active
+    short *corr_frags = nullptr;    // packed MLP weights (device)
+    float *corr_bias = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -256,6 +260,19 @@ void drop_graph(fv_ctx *c)
         k = -1;
 }
 
+// One step from buffer `from` to the other: the plain kernel, or the one
+// with the learned flux correction.
+hipError_t launch_one(fv_ctx *c, int from, hipStream_t st)
+{
+    if (c->corr_on)
+        return fvk::launch_step_learned(c->n, c->ld, c->U[from], c->U[from ^ 1], c->nb_w,
+                                        c->nb16_w, c->nrm_w, c->coef, c->inv_area_w, c->corr_frags,
+                                        c->corr_bias, c->gamma, c->narrow, c->closed, c->grid, st);
+    return fvk::launch_step(c->n, c->ld, c->U[from], c->U[from ^ 1], c->nb_w, c->nb16_w,
+                            c->nrm_w, c->coef, c->gamma, c->narrow, c->closed, c->block, c->grid,
+                            st);
+}
+
 // n_steps launches of the step, ping-ponging the state buffers; through a
 // captured graph (one launch of the whole sequence) when enabled.
 fv_status run_steps(fv_ctx *c, int32_t n_steps)
@@ -264,14 +281,13 @@ fv_status run_steps(fv_ctx *c, int32_t n_steps)
         return FV_OK;
     if (!c->use_graph) {
         for (int32_t s = 0; s < n_steps; ++s) {
-            HIP_TRY(fvk::launch_step(c->n, c->ld, c->U[c->cur], c->U[c->cur ^ 1], c->nb_w,
-                                     c->nb16_w, c->nrm_w, c->coef, c->gamma, c->narrow, c->closed,
-                                     c->block, c->grid, c->stream));
+            HIP_TRY(launch_one(c, c->cur, c->stream));
             c->cur ^= 1;
         }
         return FV_OK;
     }
-    const long long key[6] = {n_steps, c->cur, c->block, c->grid, c->narrow, c->closed};
+    const long long key[6] = {n_steps, c->cur, c->block, c->grid,
+                              c->narrow + 2 * c->closed + 4 * c->corr_on, 0};
     bool hit = c->graph_exec != nullptr;
     for (int k = 0; hit && k < 6; ++k)
         hit = key[k] == c->graph_key[k];
@@ -283,9 +299,7 @@ fv_status run_steps(fv_ctx *c, int32_t n_steps)
         int cur = c->cur;
         hipError_t err = hipSuccess;
         for (int32_t s = 0; s < n_steps && err == hipSuccess; ++s) {
-            err = fvk::launch_step(c->n, c->ld, c->U[cur], c->U[cur ^ 1], c->nb_w, c->nb16_w,
-                                   c->nrm_w, c->coef, c->gamma, c->narrow, c->closed, c->block,
-                                   c->grid, c->cap_stream);
+            err = launch_one(c, cur, c->cap_stream);
             cur ^= 1;
         }
         hipGraph_t g = nullptr;
@@ -376,6 +390,10 @@ fv_status fv_create(int64_t n_cells, double gamma, void *d_arena, size_t arena_b
     p += align_up((size_t)kMaxSegments * 8);
     c->passes_dev = reinterpret_cast<int32_t *>(p);
     p += align_up((size_t)kMaxSegments * 4);
+    c->corr_frags = reinterpret_cast<short *>(p);
+    p += align_up(fvk::kCorrFragShorts * 2);
+    c->corr_bias = reinterpret_cast<float *>(p);
+    p += align_up(fvk::kCorrBias * 4);
     c->small = p;
     *out = c;
     return FV_OK;
@@ -592,6 +610,32 @@ fv_status fv_step_adjoint(fv_ctx *c, const double *d_U, double *d_lambda, double
                                 c->nrm_o, c->area_o, dt, c->gamma, c->stream));
     HIP_TRY(hipMemcpyAsync(d_lambda, out, (size_t)c->n * sizeof(double4), hipMemcpyDeviceToDevice,
                            c->stream));
+    return FV_OK;
+}
+
+fv_status fv_set_correction(fv_ctx *c, const float *params, int32_t count)
+{
+    g_last_error.clear();
+    if (fv_status st = check_ctx(c))
+        return st;
+    if (!params) {
+        c->corr_on = false;
+        return FV_OK;
+    }
+    if (count != fvk::kCorrParams)
+        return fail(FV_EINVAL, "expected %d parameters, got %d", fvk::kCorrParams, count);
+    for (int32_t k = 0; k < count; ++k)
+        if (!std::isfinite(params[k]))
+            return fail(FV_EINVAL, "parameter %d is not finite", k);
+    std::vector<short> frags(fvk::kCorrFragShorts);
+    std::vector<float> bias(fvk::kCorrBias);
+    fvk::pack_correction(params, frags.data(), bias.data());
+    HIP_TRY(hipMemcpyAsync(c->corr_frags, frags.data(), frags.size() * sizeof(short),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->corr_bias, bias.data(), bias.size() * sizeof(float),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->corr_on = true;
     return FV_OK;
 }
 

@@ -24,12 +24,13 @@ FV_EHIP = -4
 FV_ENOMEM = -5
 FV_ORDER_IDENTITY = 0
 FV_ORDER_CM = 1
+FV_CORRECTION_PARAMS = 5252
 
 # every symbol include/fvgpu.h declares
 EXPORTS = (
     "fv_arena_bytes", "fv_create", "fv_upload_mesh", "fv_upload_batch", "fv_upload_state",
     "fv_upload_state_device", "fv_renumber", "fv_step", "fv_step_batch", "fv_step_adjoint",
-    "fv_set_launch",
+    "fv_set_correction", "fv_set_launch",
     "fv_renumber_passes", "fv_download_state", "fv_download_state_device", "fv_bytes_per_update",
     "fv_check_state", "fv_destroy", "fv_last_error",
 )
@@ -62,6 +63,7 @@ def lib() -> ctypes.CDLL:
         L.fv_step_batch.argtypes = [vp, i32, vp]
         L.fv_set_launch.argtypes = [vp, i32, i32, i32]
         L.fv_step_adjoint.argtypes = [vp, vp, vp, dbl]
+        L.fv_set_correction.argtypes = [vp, vp, i32]
         L.fv_renumber_passes.argtypes = [vp, vp]
         L.fv_upload_state.argtypes = [vp, vp]
         L.fv_upload_state_device.argtypes = [vp, vp]
@@ -134,6 +136,15 @@ def fv_step_batch(ctx: int, n_steps: int, dt) -> None:
 
 def fv_step_adjoint(ctx: int, d_U, d_lambda, dt: float) -> None:
     _check(lib().fv_step_adjoint(ctx, _ptr(d_U), _ptr(d_lambda), float(dt)))
+
+
+def fv_set_correction(ctx: int, params) -> None:
+    """params: float32 [FV_CORRECTION_PARAMS], or None for the plain step."""
+    if params is None:
+        _check(lib().fv_set_correction(ctx, None, 0))
+        return
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().fv_set_correction(ctx, _ptr(p), int(p.size)))
 
 
 def fv_set_launch(ctx: int, block: int = 256, grid: int = 0, use_graph: bool = False) -> None:
@@ -231,6 +242,9 @@ class Solver:
             fv_step(self.ctx, n_steps, float(dt))
         else:
             fv_step_batch(self.ctx, n_steps, dt)
+
+    def set_correction(self, params) -> None:
+        fv_set_correction(self.ctx, params)
 
     def set_launch(self, block: int = 256, grid: int = 0, use_graph: bool = False) -> None:
         fv_set_launch(self.ctx, block, grid, use_graph)
