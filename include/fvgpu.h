@@ -158,8 +158,10 @@ fv_status fv_step_batch(fv_ctx *ctx, int32_t n_steps, const double *dt);
  * given the state U^n at which the step is taken and the cotangent lambda of
  * U^{n+1}, overwrite lambda with the cotangent of U^n,
  *   lambda_k <- lambda_k - sum_f (dG(U_k, U_j, n_f)/dU_k)^T (c_k lambda_k - c_j lambda_j)
- * with G the face flux times |n_f| and c = dt / V.  For a batch, all meshes
- * use this dt.
+ * with G the face flux times |n_f| and c = dt / V.  When a learned
+ * correction is set (fv_set_correction), G includes it and its Jacobian
+ * (bfloat16 roundings are differentiated as the identity).  For a batch,
+ * all meshes use this dt.
  *   d_U       device double [n][4], numbering of the uploaded mesh, 32-byte aligned.
  *   d_lambda  device double [n][4], same numbering, in/out, 32-byte aligned.
  * Asynchronous on the stream; uses the context's scratch memory.
@@ -167,14 +169,27 @@ fv_status fv_step_batch(fv_ctx *ctx, int32_t n_steps, const double *dt);
 fv_status fv_step_adjoint(fv_ctx *ctx, const double *d_U, double *d_lambda, double dt);
 
 /*
+ * fv_step_adjoint that also accumulates the gradient of the loss with
+ * respect to the correction's parameters: d_grad += (dU^{n+1}/dtheta)^T
+ * lambda, in the parameter order of fv_set_correction.
+ *   d_grad  device double [FV_CORRECTION_PARAMS], 8-byte aligned, in/out;
+ *           NULL makes this fv_step_adjoint.
+ * FV_ESTATE if d_grad is given and no correction is set.  The sum over the
+ * cells is taken in a fixed order for a given mesh size, so repeated calls
+ * give the same bits.  Asynchronous on the stream.
+ */
+fv_status fv_step_adjoint_grad(fv_ctx *ctx, const double *d_U, double *d_lambda, double dt,
+                               double *d_grad);
+
+/*
  * Learned correction of the face flux (not in the paper; added to its
  * Lax-Friedrichs flux of section 6.2.2).  Per face, with e the unit normal,
  * t = (-e_y, e_x), l the face length, a = 1/V and c = dt/V of both cells:
  *   x(L, R, n) = [rho_L - 1, u.e_L, u.t_L, p_L - 1, rho_R - 1, u.e_R, u.t_R,
  *                 p_R - 1, e_x, e_y, l^2 (a_L + a_R)/2, l (c_L + c_R)/2]
- *   y(x) = W3^T h2 + b3, h2 = s(W2^T h1 + b2), h1 = s(W1^T x + b1),
- *   s(z) = z / (1 + |z|), inputs, activations and weights in bfloat16,
- *   products summed in float32;
+ *   y(x) = W3^T h2 + b3, h2 = relu(W2^T h1 + b2), h1 = relu(W1^T x + b1),
+ *   inputs, activations, weights and b1 in bfloat16, products summed in
+ *   float32;
  *   G += l (R(e) y(x(L, R, n)) - R(-e) y(x(R, L, -n))),
  *   R(e) y = (y0, y1 e_x + y2 t_x, y1 e_y + y2 t_y, y3).
  * The added flux is exactly antisymmetric across every face, so mass,

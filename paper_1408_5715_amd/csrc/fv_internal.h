@@ -44,9 +44,9 @@ hipError_t launch_adjoint(int32_t n, int32_t ld, const double4 *U, const double4
                           double4 *lam, const int32_t *nb, const double *nrm, const double *area,
                           double dt, double gamma, hipStream_t s);
 
-// Learned correction: the packed MLP (24 weight fragments of 64 lanes x 4
-// bfloat16 = kCorrFragShorts shorts, then 144 float biases) and the step
-// that adds it to the flux (see fv_learned.hip).
+// Learned correction: the packed MLP (weight fragments, kCorrFragShorts
+// bfloat16, then 144 float biases: b1, b2, b3 padded to 16) and the step that
+// adds it to the flux (see fv_learned.hip).
 constexpr int kCorrParams = 12 * 64 + 64 + 64 * 64 + 64 + 64 * 4 + 4;  // 5252
 constexpr int kCorrFragShorts = 24 * 64 * 4;
 constexpr int kCorrBias = 144;
@@ -56,6 +56,20 @@ hipError_t launch_step_learned(int32_t n, int32_t ld, const double4 *U, double4 
                                const double *coef, const double *inv_area, const short *frags,
                                const float *bias, double gamma, bool narrow, bool closed, int grid,
                                hipStream_t s);
+
+// Adjoint of the corrected step (see fv_learned.hip): lam from lam_next as
+// launch_adjoint does, plus the cotangent of the correction, on arrays in
+// any one numbering.  Each workgroup leaves its part of the parameter
+// gradient in partial [adjoint_learned_grid(n)][kCorrParams]; with grad
+// non-null, grad [kCorrParams] (float64) += the gradient.
+constexpr int kCorrAdjFragShorts = (4 * 4 + 8 * 8 + 4 * 4 + 8 * 8 + 2 * 8) * 64;
+constexpr int kCorrAdjMaxGrid = 512;
+void pack_correction_adjoint(const float *params, short *afrags);
+int adjoint_learned_grid(int32_t n);
+hipError_t launch_adjoint_learned(int32_t n, int32_t ld, const double4 *U, const double4 *lam_next,
+                                  double4 *lam, const int32_t *nb, const double *nrm,
+                                  const double *area, double dt, double gamma, const short *afrags,
+                                  const float *bias, float *partial, double *grad, hipStream_t s);
 
 // ---- renumbering --------------------------------------------------------
 // rec[v] = (nb_0[v], nb_1[v], nb_2[v], -1): the graph with an empty label slot.

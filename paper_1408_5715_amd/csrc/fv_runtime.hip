@@ -68,7 +68,9 @@ struct Layout {
         // segment offsets (int64), per-segment dt (double), per-segment pass counts (int32)
         seg = align_up((size_t)(kMaxSegments + 1) * 8) + align_up((size_t)kMaxSegments * 8) +
               align_up((size_t)kMaxSegments * 4);
-        corr = align_up(fvk::kCorrFragShorts * 2) + align_up(fvk::kCorrBias * 4);
+        corr = align_up(fvk::kCorrFragShorts * 2) + align_up(fvk::kCorrBias * 4) +
+               align_up(fvk::kCorrAdjFragShorts * 2) +
+               align_up((size_t)fvk::kCorrAdjMaxGrid * fvk::kCorrParams * 4);
         small = kAlign;
         total = 2 * U + 2 * nb + nb16 + 2 * nrm + 3 * area + 2 * idx + scratch + seg + corr + small;
     }
@@ -112,6 +114,8 @@ struct fv_ctx {
     bool corr_on = false;           // learned flux correction active
     short *corr_frags = nullptr;    // packed MLP weights (device)
     float *corr_bias = nullptr;
+    short *corr_afrags = nullptr;   // fragments of the adjoint kernel
+    float *corr_partial = nullptr;  // per-workgroup parameter gradients
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -394,6 +398,10 @@ fv_status fv_create(int64_t n_cells, double gamma, void *d_arena, size_t arena_b
     p += align_up(fvk::kCorrFragShorts * 2);
     c->corr_bias = reinterpret_cast<float *>(p);
     p += align_up(fvk::kCorrBias * 4);
+    c->corr_afrags = reinterpret_cast<short *>(p);
+    p += align_up(fvk::kCorrAdjFragShorts * 2);
+    c->corr_partial = reinterpret_cast<float *>(p);
+    p += align_up((size_t)fvk::kCorrAdjMaxGrid * fvk::kCorrParams * 4);
     c->small = p;
     *out = c;
     return FV_OK;
@@ -593,6 +601,12 @@ fv_status fv_step_batch(fv_ctx *c, int32_t n_steps, const double *dt)
 
 fv_status fv_step_adjoint(fv_ctx *c, const double *d_U, double *d_lambda, double dt)
 {
+    return fv_step_adjoint_grad(c, d_U, d_lambda, dt, nullptr);
+}
+
+fv_status fv_step_adjoint_grad(fv_ctx *c, const double *d_U, double *d_lambda, double dt,
+                               double *d_grad)
+{
     g_last_error.clear();
     if (fv_status st = check_ctx(c))
         return st;
@@ -604,10 +618,20 @@ fv_status fv_step_adjoint(fv_ctx *c, const double *d_U, double *d_lambda, double
         return fail(FV_EINVAL, "dt %g must be finite and > 0", dt);
     if (!c->mesh_ready)
         return fail(FV_ESTATE, "upload the mesh first");
+    if (d_grad && reinterpret_cast<uintptr_t>(d_grad) % 8 != 0)
+        return fail(FV_EINVAL, "gradient array must be 8-byte aligned");
+    if (d_grad && !c->corr_on)
+        return fail(FV_ESTATE, "no correction is set: there is no parameter gradient");
     double4 *out = reinterpret_cast<double4 *>(c->scratch);
-    HIP_TRY(fvk::launch_adjoint(c->n, c->ld, reinterpret_cast<const double4 *>(d_U),
-                                reinterpret_cast<const double4 *>(d_lambda), out, c->nb_o,
-                                c->nrm_o, c->area_o, dt, c->gamma, c->stream));
+    if (c->corr_on)
+        HIP_TRY(fvk::launch_adjoint_learned(
+            c->n, c->ld, reinterpret_cast<const double4 *>(d_U),
+            reinterpret_cast<const double4 *>(d_lambda), out, c->nb_o, c->nrm_o, c->area_o, dt,
+            c->gamma, c->corr_afrags, c->corr_bias, c->corr_partial, d_grad, c->stream));
+    else
+        HIP_TRY(fvk::launch_adjoint(c->n, c->ld, reinterpret_cast<const double4 *>(d_U),
+                                    reinterpret_cast<const double4 *>(d_lambda), out, c->nb_o,
+                                    c->nrm_o, c->area_o, dt, c->gamma, c->stream));
     HIP_TRY(hipMemcpyAsync(d_lambda, out, (size_t)c->n * sizeof(double4), hipMemcpyDeviceToDevice,
                            c->stream));
     return FV_OK;
@@ -627,10 +651,13 @@ fv_status fv_set_correction(fv_ctx *c, const float *params, int32_t count)
     for (int32_t k = 0; k < count; ++k)
         if (!std::isfinite(params[k]))
             return fail(FV_EINVAL, "parameter %d is not finite", k);
-    std::vector<short> frags(fvk::kCorrFragShorts);
+    std::vector<short> frags(fvk::kCorrFragShorts), afrags(fvk::kCorrAdjFragShorts);
     std::vector<float> bias(fvk::kCorrBias);
     fvk::pack_correction(params, frags.data(), bias.data());
+    fvk::pack_correction_adjoint(params, afrags.data());
     HIP_TRY(hipMemcpyAsync(c->corr_frags, frags.data(), frags.size() * sizeof(short),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->corr_afrags, afrags.data(), afrags.size() * sizeof(short),
                            hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->corr_bias, bias.data(), bias.size() * sizeof(float),
                            hipMemcpyHostToDevice, c->stream));

@@ -30,7 +30,7 @@ FV_CORRECTION_PARAMS = 5252
 EXPORTS = (
     "fv_arena_bytes", "fv_create", "fv_upload_mesh", "fv_upload_batch", "fv_upload_state",
     "fv_upload_state_device", "fv_renumber", "fv_step", "fv_step_batch", "fv_step_adjoint",
-    "fv_set_correction", "fv_set_launch",
+    "fv_step_adjoint_grad", "fv_set_correction", "fv_set_launch",
     "fv_renumber_passes", "fv_download_state", "fv_download_state_device", "fv_bytes_per_update",
     "fv_check_state", "fv_destroy", "fv_last_error",
 )
@@ -63,6 +63,7 @@ def lib() -> ctypes.CDLL:
         L.fv_step_batch.argtypes = [vp, i32, vp]
         L.fv_set_launch.argtypes = [vp, i32, i32, i32]
         L.fv_step_adjoint.argtypes = [vp, vp, vp, dbl]
+        L.fv_step_adjoint_grad.argtypes = [vp, vp, vp, dbl, vp]
         L.fv_set_correction.argtypes = [vp, vp, i32]
         L.fv_renumber_passes.argtypes = [vp, vp]
         L.fv_upload_state.argtypes = [vp, vp]
@@ -136,6 +137,12 @@ def fv_step_batch(ctx: int, n_steps: int, dt) -> None:
 
 def fv_step_adjoint(ctx: int, d_U, d_lambda, dt: float) -> None:
     _check(lib().fv_step_adjoint(ctx, _ptr(d_U), _ptr(d_lambda), float(dt)))
+
+
+def fv_step_adjoint_grad(ctx: int, d_U, d_lambda, dt: float, d_grad) -> None:
+    """d_grad: float64 device tensor [FV_CORRECTION_PARAMS], accumulated."""
+    _check(lib().fv_step_adjoint_grad(ctx, _ptr(d_U), _ptr(d_lambda), float(dt),
+                                      None if d_grad is None else _ptr(d_grad)))
 
 
 def fv_set_correction(ctx: int, params) -> None:

@@ -55,6 +55,7 @@ def main() -> int:
     lines.append("| kernel | launches | FETCH MiB/launch (scaled) | WRITE MiB/launch (scaled) | "
                  "bytes/cell (scaled) |")
     lines.append("|---|---|---|---|---|")
+    step = None
     for k in sorted(f):
         if k == copy or k not in w:
             continue
@@ -62,6 +63,18 @@ def main() -> int:
         wb = st.mean(w[k]) * 1024 * ws
         lines.append(f"| {k} | {len(f[k])} | {fb / 2**20:.1f} | {wb / 2**20:.1f} | "
                      f"{(fb + wb) / CELLS:.1f} |")
+        if "fv_step_kernel" in k:
+            step = (round(fb), round(wb))
+    if step:
+        lines.append("")
+        lines.append(f"fv_step_kernel per launch (scaled): fetch {step[0]:,} B + write {step[1]:,} B "
+                     f"= {step[0] + step[1]:,} B")
+    log = os.path.join(OUT, "prof_trace.log")
+    if os.path.exists(log):
+        for line in open(log):
+            if line.startswith("{"):
+                lines.append("")
+                lines.append("bench.py line of the traced run: `" + line.strip() + "`")
     print("\n".join(lines))
     return 0
 
