@@ -164,6 +164,76 @@ def bench_batch(args, dev) -> int:
     return 0
 
 
+# Useful multiply-adds of one MLP row (12 -> 64 -> 64 -> 4); a cell evaluates
+# 6 rows (3 faces, both orientations).
+MLP_FLOPS_PER_CELL = 6 * 2 * (12 * 64 + 64 * 64 + 64 * 4)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def bench_learned(args, dev) -> int:
+    """The learned-correction comparison: the corrected coarse solver
+    (1024 x 1024 quads) and the plain fine solver (2048 x 2048) from the same
+    seeded flows, errors of the coarse solvers against the restricted fine
+    solution after 64, 256 and 2000 coarse steps, and the step rate of each."""
+    import numpy as np
+
+    from paper_1408_5715_amd import learned
+
+    N = 1024 if args.N == 1024 else args.N
+    steps = 2000 if args.fv_steps == 1000 else args.fv_steps
+    seeds = [5000, 5001]
+    p = learned.load_params()
+    horizons = sorted({64, 256, steps})
+    errs = {}
+    timing = None
+    for hz in horizons:
+        res = learned.compare(p, N, 2, seeds, hz, timing_steps=200 if hz == steps else 0)
+        errs[hz] = res["flows"]
+        if hz == steps:
+            timing = res
+    cc = timing["coarse_corrected"]["cell_updates_per_s"]
+    fp = timing["fine_plain"]["cell_updates_per_s"]
+    cp = timing["coarse_plain"]["cell_updates_per_s"]
+    t_coarse = steps / (cc / timing["coarse_cells"])
+    t_fine = 2 * steps / (fp / timing["fine_cells"])
+    achieved = MLP_FLOPS_PER_CELL * cc / 1e12
+    rec = {
+        "metric": "learned vs plain at equal L2 density error",
+        "value": cc,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": timing["coarse_corrected"]["us_per_step"] / 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 flux and update, bf16 MLP with f32 accumulation",
+        "data": "synthetic",
+        "config": {"workload": (f"learned-corrected {N}x{N}-quad coarse mesh vs plain "
+                                f"{2 * N}x{2 * N} fine mesh (unjittered, nested), {steps} coarse "
+                                f"steps, seeded vortex + bump flows {seeds}"),
+                   "coarse_cells": timing["coarse_cells"], "fine_cells": timing["fine_cells"],
+                   "coarse_steps": steps, "dt_coarse": timing["dt_coarse"]},
+        "roofline": {"bound": "mfma", "kernel": "fv_step_learned_kernel", "achieved": achieved,
+                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_cell_update": MLP_FLOPS_PER_CELL},
+        "cpu_baseline": None,
+        "comparison": {
+            "fine_plain_cell_updates_per_s": fp,
+            "coarse_plain_cell_updates_per_s": cp,
+            "time_to_solution_fine_over_coarse_corrected": t_fine / t_coarse,
+            "l2_rho_vs_fine": {str(hz): [{"plain": f["l2_rho_plain_vs_fine"],
+                                          "corrected": f["l2_rho_corrected_vs_fine"],
+                                          "ratio": f["ratio"]} for f in errs[hz]]
+                               for hz in horizons},
+        },
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,9 +245,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-random", action="store_true",
                     help="skip timing the step on the random (not renumbered) order")
-    ap.add_argument("--workload", choices=("single", "batch"), default="single",
+    ap.add_argument("--workload", choices=("single", "batch", "learned"), default="single",
                     help="single: the 1024x1024-quad job (default line); batch: 64 meshes of "
-                         "20k-500k cells advanced together")
+                         "20k-500k cells advanced together; learned: the corrected 1024x1024 "
+                         "solver against the plain 2048x2048 one")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -200,6 +271,8 @@ def main() -> int:
     torch.cuda.set_device(dev)
     if args.workload == "batch":
         return bench_batch(args, dev)
+    if args.workload == "learned":
+        return bench_learned(args, dev)
 
     N = args.N
     log(f"generating the {N}x{N}-quad mesh")

@@ -106,3 +106,84 @@ def cfl_dt(P: Primitive, area: np.ndarray, perimeter: np.ndarray, cfl: float = 0
     c = np.sqrt(gamma * P.p / P.rho)
     speed = np.sqrt(P.u * P.u + P.v * P.v) + c
     return float(cfl * np.min(area / (perimeter * speed)))
+
+
+def _buckets(centroid: np.ndarray, L: float, reach: float):
+    """Cells grouped by square buckets of side >= reach (for local sums)."""
+    nb = int(L // reach)
+    if nb < 3:
+        return None
+    b = L / nb
+    bx = np.floor(centroid[:, 0] / b).astype(np.int64) % nb
+    by = np.floor(centroid[:, 1] / b).astype(np.int64) % nb
+    key = bx * nb + by
+    order = np.argsort(key, kind="stable")
+    start = np.searchsorted(key[order], np.arange(nb * nb + 1))
+    return nb, b, order, start
+
+
+def _near(bk, n: int, x: float, y: float) -> np.ndarray:
+    """Indices of the cells in the 3 x 3 buckets around (x, y)."""
+    if bk is None:
+        return np.arange(n)
+    nb, b, order, start = bk
+    ix, iy = int(x // b) % nb, int(y // b) % nb
+    parts = [order[start[((ix + a) % nb) * nb + (iy + c) % nb]:
+                   start[((ix + a) % nb) * nb + (iy + c) % nb + 1]]
+             for a in (-1, 0, 1) for c in (-1, 0, 1)]
+    return np.concatenate(parts)
+
+
+def flow_primitive(centroid: np.ndarray, h: float, seed: int, L: float = 10.0,
+                   gamma: float = GAMMA) -> Primitive:
+    """A seeded flow whose features are sized in mesh cells (h = quad side),
+    so that meshes of different resolution see the same local structure:
+
+    a uniform stream (rho = p = 1, speed U[0.2, 0.6] sqrt(gamma), direction
+    U[0, 2 pi)) carrying isentropic vortices (core radius R ~ h U[4, 8],
+    strength beta ~ U[2, 4], random sign) and Gaussian density/pressure bumps
+    (amplitude U[0.01, 0.1], width h U[2, 6]), 3 vortices and 12 bumps per
+    128 x 128 quads of area.  Vortex velocities and temperature deficits
+    superpose: u = u_inf + sum du_k, T = 1 - sum dT_k, rho = T^(1/(gamma-1))
+    + sum bumps, p = rho_v T + sum bumps (rho_v = T^(1/(gamma-1))).  Each
+    feature is truncated beyond 6 of its radii (relative size < 2e-8)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = centroid.shape[0]
+    quads = (L / h) ** 2
+    n_vort = max(1, int(round(3 * quads / 128 ** 2)))
+    n_bump = max(1, int(round(12 * quads / 128 ** 2)))
+    speed = rng.uniform(0.2, 0.6) * math.sqrt(gamma)
+    ang = rng.uniform(0.0, 2.0 * math.pi)
+    vc = rng.uniform(0.0, L, size=(n_vort, 2))
+    vR = h * rng.uniform(4.0, 8.0, size=n_vort)
+    vb = rng.uniform(2.0, 4.0, size=n_vort) * rng.choice([-1.0, 1.0], size=n_vort)
+    bc = rng.uniform(0.0, L, size=(n_bump, 2))
+    ba = rng.uniform(0.01, 0.1, size=n_bump)
+    bw = h * rng.uniform(2.0, 6.0, size=n_bump)
+
+    du = np.zeros(n)
+    dv = np.zeros(n)
+    dT = np.zeros(n)
+    s = np.zeros(n)
+    bk = _buckets(centroid, L, 6.0 * 8.0 * h)
+    for k in range(n_vort):
+        idx = _near(bk, n, vc[k, 0], vc[k, 1])
+        dx = _nearest_image(centroid[idx, 0] - vc[k, 0], L) / vR[k]
+        dy = _nearest_image(centroid[idx, 1] - vc[k, 1], L) / vR[k]
+        r2 = dx * dx + dy * dy
+        f = np.where(r2 < 36.0, np.exp(0.5 * (1.0 - r2)), 0.0)
+        c = vb[k] / (2.0 * math.pi)
+        du[idx] -= c * dy * f
+        dv[idx] += c * dx * f
+        dT[idx] += (gamma - 1.0) * vb[k] ** 2 / (8.0 * gamma * math.pi ** 2) * f * f
+    for k in range(n_bump):
+        idx = _near(bk, n, bc[k, 0], bc[k, 1])
+        dx = _nearest_image(centroid[idx, 0] - bc[k, 0], L) / bw[k]
+        dy = _nearest_image(centroid[idx, 1] - bc[k, 1], L) / bw[k]
+        r2 = dx * dx + dy * dy
+        s[idx] += ba[k] * np.where(r2 < 36.0, np.exp(-0.5 * r2), 0.0)
+    T = 1.0 - dT
+    if np.min(T) <= 0.05:
+        raise ValueError("vortices overlap too strongly for this seed")
+    rv = T ** (1.0 / (gamma - 1.0))
+    return Primitive(rv + s, speed * math.cos(ang) + du, speed * math.sin(ang) + dv, rv * T + s)

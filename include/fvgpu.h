@@ -204,6 +204,23 @@ fv_status fv_step_adjoint_grad(fv_ctx *ctx, const double *d_U, double *d_lambda,
 fv_status fv_set_correction(fv_ctx *ctx, const float *params, int32_t count);
 
 /*
+ * Weighted gather of states from one mesh onto another, the area-weighted
+ * restriction of a fine solution to a coarse mesh that nests it (the
+ * training targets of the learned correction):
+ *   out[i] = sum_{m<k} w[i][m] src[idx[i][m]]   (all four components, m in order)
+ *   d_src  device double [n_src][4], 32-byte aligned;
+ *   d_idx  device int32 [n][k]; d_w device double [n][k] (for a restriction,
+ *          the fine cells' areas over the coarse cell's area);
+ *   d_out  device double [n][4], 32-byte aligned, must not overlap d_src.
+ * A row with an index outside [0, n_src) is written as NaN (nothing is read
+ * for that index).  FV_EINVAL on null, misaligned or bad sizes (1 <= k <=
+ * 1024).  Needs no context; asynchronous on hip_stream (NULL: the null
+ * stream).
+ */
+fv_status fv_restrict(const double *d_src, int64_t n_src, const int32_t *d_idx, const double *d_w,
+                      int64_t n, int32_t k, double *d_out, void *hip_stream);
+
+/*
  * Launch shape of the step kernel (no effect on results, which are bitwise
  * independent of it).
  *   block      workgroup size: 128, 256 (default) or 512 cells.

@@ -110,6 +110,11 @@ hipError_t launch_gather_state(int32_t n, const int32_t *idx, const double4 *src
 hipError_t launch_gather_state2(int32_t n, const int32_t *idx_a, const int32_t *idx_b,
                                 const double4 *src, double4 *dst, hipStream_t s);
 
+// out[i] = sum_m w[i][m] src[idx[i][m]], m = 0..k-1 in order; NaN where an
+// index is outside [0, n_src).
+hipError_t launch_restrict(int64_t n, int32_t k, int64_t n_src, const double4 *src,
+                           const int32_t *idx, const double *w, double4 *out, hipStream_t s);
+
 // *flag = 1 if any cell has non-finite or non-positive rho or p (flag must be 0 before).
 hipError_t launch_check_state(int32_t n, const double4 *U, double gamma, int32_t *flag,
                               hipStream_t s);

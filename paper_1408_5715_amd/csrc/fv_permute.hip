@@ -93,7 +93,48 @@ __global__ void check_state_kernel(int32_t n, const double4 *__restrict__ U, dou
         *flag = 1;  // every writer stores the same value
 }
 
+// Weighted gather: out[i] = sum_m w[i][m] src[idx[i][m]] (m in order); an
+// index outside [0, n_src) makes out[i] NaN instead of being read.
+__global__ void restrict_kernel(int64_t n, int32_t k, int64_t n_src, const double4 *__restrict__ src,
+                                const int32_t *__restrict__ idx, const double *__restrict__ w,
+                                double4 *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    double4 a = {0.0, 0.0, 0.0, 0.0};
+    bool ok = true;
+    for (int32_t m = 0; m < k; ++m) {
+        const int32_t j = idx[i * k + m];
+        if (j < 0 || j >= n_src) {
+            ok = false;
+            continue;
+        }
+        const double wm = w[i * k + m];
+        const double4 u = src[j];
+        a.x += wm * u.x;
+        a.y += wm * u.y;
+        a.z += wm * u.z;
+        a.w += wm * u.w;
+    }
+    if (!ok) {
+        const double nan = __builtin_nan("");
+        a = {nan, nan, nan, nan};
+    }
+    out[i] = a;
+}
+
 }  // namespace
+
+hipError_t launch_restrict(int64_t n, int32_t k, int64_t n_src, const double4 *src,
+                           const int32_t *idx, const double *w, double4 *out, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(restrict_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, s, n, k, n_src, src, idx, w, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_nb_aos_to_soa(int32_t n, int32_t ld, const int32_t *aos, int32_t *soa,
                                 hipStream_t s)

@@ -756,6 +756,24 @@ fv_status fv_check_state(fv_ctx *c)
     return FV_OK;
 }
 
+fv_status fv_restrict(const double *d_src, int64_t n_src, const int32_t *d_idx, const double *d_w,
+                      int64_t n, int32_t k, double *d_out, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!d_src || !d_idx || !d_w || !d_out)
+        return fail(FV_EINVAL, "null device array");
+    if (n <= 0 || n_src <= 0 || k < 1 || k > 1024 || n > INT32_MAX || n_src > INT32_MAX)
+        return fail(FV_EINVAL, "bad sizes n=%lld n_src=%lld k=%d", (long long)n,
+                    (long long)n_src, k);
+    if (reinterpret_cast<uintptr_t>(d_src) % 32 != 0 || reinterpret_cast<uintptr_t>(d_out) % 32 != 0 ||
+        reinterpret_cast<uintptr_t>(d_idx) % 4 != 0 || reinterpret_cast<uintptr_t>(d_w) % 8 != 0)
+        return fail(FV_EINVAL, "misaligned device array");
+    HIP_TRY(fvk::launch_restrict(n, k, n_src, reinterpret_cast<const double4 *>(d_src), d_idx, d_w,
+                                 reinterpret_cast<double4 *>(d_out),
+                                 reinterpret_cast<hipStream_t>(hip_stream)));
+    return FV_OK;
+}
+
 fv_status fv_destroy(fv_ctx *c)
 {
     g_last_error.clear();

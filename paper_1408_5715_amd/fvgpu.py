@@ -30,7 +30,7 @@ FV_CORRECTION_PARAMS = 5252
 EXPORTS = (
     "fv_arena_bytes", "fv_create", "fv_upload_mesh", "fv_upload_batch", "fv_upload_state",
     "fv_upload_state_device", "fv_renumber", "fv_step", "fv_step_batch", "fv_step_adjoint",
-    "fv_step_adjoint_grad", "fv_set_correction", "fv_set_launch",
+    "fv_step_adjoint_grad", "fv_set_correction", "fv_restrict", "fv_set_launch",
     "fv_renumber_passes", "fv_download_state", "fv_download_state_device", "fv_bytes_per_update",
     "fv_check_state", "fv_destroy", "fv_last_error",
 )
@@ -64,6 +64,7 @@ def lib() -> ctypes.CDLL:
         L.fv_set_launch.argtypes = [vp, i32, i32, i32]
         L.fv_step_adjoint.argtypes = [vp, vp, vp, dbl]
         L.fv_step_adjoint_grad.argtypes = [vp, vp, vp, dbl, vp]
+        L.fv_restrict.argtypes = [vp, i64, vp, vp, i64, i32, vp, vp]
         L.fv_set_correction.argtypes = [vp, vp, i32]
         L.fv_renumber_passes.argtypes = [vp, vp]
         L.fv_upload_state.argtypes = [vp, vp]
@@ -143,6 +144,14 @@ def fv_step_adjoint_grad(ctx: int, d_U, d_lambda, dt: float, d_grad) -> None:
     """d_grad: float64 device tensor [FV_CORRECTION_PARAMS], accumulated."""
     _check(lib().fv_step_adjoint_grad(ctx, _ptr(d_U), _ptr(d_lambda), float(dt),
                                       None if d_grad is None else _ptr(d_grad)))
+
+
+def fv_restrict(d_src, d_idx, d_w, d_out, stream=None) -> None:
+    """d_out[i] = sum_m d_w[i, m] d_src[d_idx[i, m]] (device tensors: src
+    float64 [n_src, 4], idx int32 [n, k], w float64 [n, k], out float64 [n, 4])."""
+    n, k = d_idx.shape
+    _check(lib().fv_restrict(_ptr(d_src), int(d_src.shape[0]), _ptr(d_idx), _ptr(d_w), int(n),
+                             int(k), _ptr(d_out), None if stream is None else stream.cuda_stream))
 
 
 def fv_set_correction(ctx: int, params) -> None:

@@ -58,3 +58,40 @@ def test_initial_states():
     assert np.all(B.rho >= 1.0) and np.all(B.p == B.rho)
     dt = ic.cfl_dt(P, m.area, m.perimeter)
     assert 0 < dt < 0.01
+
+
+def test_nested_restriction_covers_each_fine_cell_once():
+    """Every fine cell lies inside the coarse cell it is restricted to (its
+    centroid, barycentric test on the coarse triangle's unwrapped vertices),
+    each fine cell is used once, and the weights are area fractions."""
+    from fvgen.nested import nested_pair
+
+    for N, r in ((3, 2), (4, 4)):
+        c, f, idx, w = nested_pair(N, r)
+        assert idx.shape == (c.n, r * r)
+        assert np.array_equal(np.sort(idx.ravel()), np.arange(f.n))
+        assert np.allclose(w.sum(1), 1.0, rtol=0, atol=1e-9)  # coordinates snapped to 2^-32
+        v = c.verts  # [n, 3, 2]
+        p = f.centroid[idx]  # [n, r^2, 2]
+        p = v[:, None, 0] + np.mod(p - v[:, None, 0] + 5.0, 10.0) - 5.0
+        e1, e2 = v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]
+        d = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]
+        q = p - v[:, None, 0]
+        l1 = (q[..., 0] * e2[:, None, 1] - q[..., 1] * e2[:, None, 0]) / d[:, None]
+        l2 = (e1[:, None, 0] * q[..., 1] - e1[:, None, 1] * q[..., 0]) / d[:, None]
+        assert np.all(l1 > 0) and np.all(l2 > 0) and np.all(l1 + l2 < 1)
+
+
+def test_flow_features_scale_with_the_given_cell_size():
+    """flow_primitive sizes its features by h: the same seed and h give the
+    same flow on nested meshes (the coarse state is close to the restricted
+    fine one), and the state is physical."""
+    from fvgen.nested import nested_pair
+
+    c, f, idx, w = nested_pair(32, 2)
+    h = 10.0 / 32
+    Pc = ic.flow_primitive(c.centroid, h, 5)
+    Pf = ic.flow_primitive(f.centroid, h, 5)
+    rf = np.sum(w * Pf.rho[idx], 1)
+    assert np.all(Pc.rho > 0) and np.all(Pc.p > 0) and np.all(Pf.p > 0)
+    assert np.max(np.abs(rf - Pc.rho)) < 0.05 * np.max(np.abs(Pc.rho - 1.0))
