@@ -720,7 +720,18 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restric
     if (p >= kCorrParams)
         return;
     double s = 0.0;
-    for (int k = 0; k < slots; ++k)
+    int k = 0;
+    // loads issued 16 at a time, sums kept in slot order
+    for (; k + 16 <= slots; k += 16) {
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            v[q] = partial[(size_t)(k + q) * kCorrParams + p];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            s += (double)v[q];
+    }
+    for (; k < slots; ++k)
         s += (double)partial[(size_t)k * kCorrParams + p];
     out[p] += scale * s;
 }

@@ -3,14 +3,35 @@
 # with its default 1000-step jobs and the random-order timing skipped, so
 # every step launch runs on the renumbered mesh): a kernel trace with per-kernel statistics, then one
 # counter pass each for FETCH_SIZE and WRITE_SIZE, with a plain 256 MiB copy
-# in the same run as the calibration.  Output: gpurun_out/prof_* under the
+# in the same run as the calibration, then L2 hits and misses of the step on
+# the random order and on the renumbered order.  Output: gpurun_out/prof_* under the
 # repository root.  Summarise with: python -m paper_1408_5715_amd.profile_summary
+#
+# `profile.sh learned`: the same three runs for the learned-correction
+# kernels (paper_1408_5715_amd/profile_learned.py: 20 corrected steps on the
+# 1024 x 1024 mesh, 4 corrected adjoint steps on the 32-flow training batch),
+# with MFMA counters in place of the byte counters.  Output gpurun_out/lprof_*.
 set -euo pipefail
 ROOT="$(cd "$(dirname "$0")/.." && pwd)"
 OUT="$ROOT/gpurun_out"
 mkdir -p "$OUT"
 export TMPDIR=/tmp
+export PYTHONPATH="$ROOT${PYTHONPATH:+:$PYTHONPATH}"
 cd /tmp
+if [ "${1:-}" = "learned" ]; then
+    echo "[profile] learned: kernel trace" >&2
+    timeout -k 10 300 rocprofv3 --kernel-trace --stats -f csv -d "$OUT/lprof_trace" -o trace -- \
+        python3 -m paper_1408_5715_amd.profile_learned --adjoint > "$OUT/lprof_trace.log" 2>&1
+    echo "[profile] learned: MFMA counters" >&2
+    timeout -s KILL 120 rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_MFMA SQ_INSTS_VALU_MFMA_MOPS_BF16 \
+        SQ_VALU_MFMA_BUSY_CYCLES SQ_WAVES SQ_INSTS_LDS GRBM_GUI_ACTIVE -f csv -d "$OUT/lprof_mfma" \
+        -o mfma -- python3 -m paper_1408_5715_amd.profile_learned --adjoint > "$OUT/lprof_mfma.log" 2>&1
+    echo "[profile] learned: byte counters" >&2
+    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -f csv -d "$OUT/lprof_fetch" -o fetch -- \
+        python3 -m paper_1408_5715_amd.profile_learned --probe-copy > "$OUT/lprof_fetch.log" 2>&1
+    echo "[profile] done" >&2
+    exit 0
+fi
 echo "[profile] kernel trace" >&2
 timeout -k 10 300 rocprofv3 --kernel-trace --stats -f csv -d "$OUT/prof_trace" -o trace -- \
     python3 "$ROOT/bench.py" --steps 3 --warmup 1 --no-cpu-baseline --skip-random \
@@ -23,4 +44,8 @@ echo "[profile] WRITE_SIZE" >&2
 timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -f csv -d "$OUT/prof_write" -o write -- \
     python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random \
     --probe-copy > "$OUT/prof_write.log" 2>&1
+echo "[profile] L2 hits and misses (random order, then renumbered)" >&2
+timeout -s KILL 120 rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d "$OUT/prof_l2" -o l2 -- \
+    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline \
+    > "$OUT/prof_l2.log" 2>&1
 echo "[profile] done" >&2

@@ -17,11 +17,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 OUT = os.path.join(ROOT, "gpurun_out")
 COPY_BYTES = 256 * 2**20
 CELLS = 2097152
+SIMDS = 1024  # 256 CUs x 4; SQ_VALU_MFMA_BUSY_CYCLES sums over them
+XCDS = 8  # GRBM_GUI_ACTIVE sums over the XCDs
 
 
 def short(name: str) -> str:
     name = name.replace("fvk::(anonymous namespace)::", "")
-    return name.split("(")[0] if "elementwise" not in name else "torch elementwise copy (mul by 1)"
+    if "elementwise" in name:
+        return ("torch elementwise copy (mul by 1)" if "MulFunctor" in name or "mul" in name.lower()
+                else "torch elementwise " + name.split("<")[1].split(",")[1].strip()
+                if "<" in name else "torch elementwise")
+    return name.split("(")[0]
 
 
 def counters(path, counter):
@@ -69,6 +75,18 @@ def main() -> int:
         lines.append("")
         lines.append(f"fv_step_kernel per launch (scaled): fetch {step[0]:,} B + write {step[1]:,} B "
                      f"= {step[0] + step[1]:,} B")
+    l2 = os.path.join(OUT, "prof_l2", "l2_counter_collection.csv")
+    if os.path.exists(l2):
+        hit = counters(l2, "TCC_HIT_sum")
+        miss = counters(l2, "TCC_MISS_sum")
+        lines.append("")
+        lines.append("| step kernel variant | launches | L2 hits / launch | L2 misses / launch | "
+                     "L2 hit rate |")
+        lines.append("|---|---|---|---|---|")
+        for k in sorted(hit):
+            if "fv_step_kernel" in k and k in miss:
+                h, m = st.mean(hit[k]), st.mean(miss[k])
+                lines.append(f"| {k} | {len(hit[k])} | {h:.4g} | {m:.4g} | {h / (h + m):.3f} |")
     log = os.path.join(OUT, "prof_trace.log")
     if os.path.exists(log):
         for line in open(log):
@@ -79,5 +97,56 @@ def main() -> int:
     return 0
 
 
+def main_learned() -> int:
+    """Summary of `profile.sh learned`."""
+    lines = []
+    stats = list(csv.DictReader(open(os.path.join(OUT, "lprof_trace", "trace_kernel_stats.csv"))))
+    lines.append("| kernel | calls | avg us | min us | max us | share |")
+    lines.append("|---|---|---|---|---|---|")
+    for r in stats:
+        lines.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['Percentage']):.1f}% |")
+    for line in open(os.path.join(OUT, "lprof_trace.log")):
+        if line.startswith("corrected"):
+            lines.append("")
+            lines.append("Same process, HIP events: " + line.strip())
+    path = os.path.join(OUT, "lprof_mfma", "mfma_counter_collection.csv")
+    per = {}
+    for r in csv.DictReader(open(path)):
+        per.setdefault(short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+            float(r["Counter_Value"]))
+    lines.append("")
+    lines.append("| kernel | launches | waves | MFMA / wave | other VALU / wave | LDS / wave | "
+                 "bf16 MFMA flop / launch | MFMA busy cycles per SIMD / GPU cycles |")
+    lines.append("|---|---|---|---|---|---|---|---|")
+    for k in sorted(per):
+        c = {n: st.mean(v) for n, v in per[k].items()}
+        if not c.get("SQ_INSTS_MFMA"):
+            continue
+        w = c["SQ_WAVES"]
+        lines.append(f"| {k} | {len(per[k]['SQ_WAVES'])} | {w:.0f} | {c['SQ_INSTS_MFMA'] / w:.0f} | "
+                     f"{(c['SQ_INSTS_VALU'] - c['SQ_INSTS_MFMA']) / w:.0f} | "
+                     f"{c['SQ_INSTS_LDS'] / w:.0f} | {c['SQ_INSTS_VALU_MFMA_MOPS_BF16'] * 512:.4g} | "
+                     f"{(c['SQ_VALU_MFMA_BUSY_CYCLES'] / SIMDS) / (c['GRBM_GUI_ACTIVE'] / XCDS):.2f} |")
+    f = counters(os.path.join(OUT, "lprof_fetch", "fetch_counter_collection.csv"), "FETCH_SIZE")
+    copy = "torch elementwise copy (mul by 1)"
+    if copy in f:
+        fcopy = st.mean(f[copy][1:] if len(f[copy]) > 1 else f[copy]) * 1024
+        fs = COPY_BYTES / fcopy
+        lines.append("")
+        lines.append(f"FETCH_SIZE of the 256 MiB copy in the same run: {fcopy / 2**20:.1f} MiB "
+                     f"(scale x{fs:.3f}).")
+        for k in sorted(f):
+            if "learned" in k:
+                fb = st.mean(f[k]) * 1024 * fs
+                lines.append(f"{k}: {fb / 2**20:.1f} MiB fetched per launch (scaled), "
+                             f"{fb / CELLS:.1f} B per cell")
+    print("\n".join(lines))
+    return 0
+
+
 if __name__ == "__main__":
+    if len(sys.argv) > 1 and sys.argv[1] == "learned":
+        sys.exit(main_learned())
     sys.exit(main())
