@@ -37,6 +37,8 @@ class Oracle:
         L.oracle_am1_order.argtypes = [i64, vp, vp]
         L.oracle_am1_order.restype = ctypes.c_int
         L.oracle_bandwidth.argtypes = [i64, vp, vp, vp]
+        L.oracle_am1_bounded.argtypes = [i64, vp, i64, vp, vp, i64, vp, i64, vp, vp]
+        L.oracle_am1_bounded.restype = ctypes.c_int
         L.oracle_bandwidth.restype = ctypes.c_int
         self.lib = L
         self.path = path
@@ -88,6 +90,26 @@ class Oracle:
             raise RuntimeError("oracle_am1_order failed")
         return perm
 
+    def am1_bounded(self, nbr, bound: int, cap_factor: int = 16) -> dict:
+        """Access pattern of serial bandwidth <= bound (section 4.3): idx
+        (vertex of each load), ex (1 where that load executes it),
+        part_begin (offsets of the parts), perfect (per vertex)."""
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        n = nbr.shape[0]
+        cap = cap_factor * n
+        idx = np.empty(cap, dtype=np.int32)
+        ex = np.empty(cap, dtype=np.uint8)
+        part_begin = np.empty(n + 1, dtype=np.int64)
+        perfect = np.empty(n, dtype=np.uint8)
+        counts = np.zeros(2, dtype=np.int64)
+        rc = self.lib.oracle_am1_bounded(n, _p(nbr), int(bound), _p(idx), _p(ex), cap,
+                                         _p(part_begin), n + 1, _p(perfect), _p(counts))
+        if rc != 0:
+            raise RuntimeError(f"oracle_am1_bounded failed ({rc})")
+        m, parts = int(counts[0]), int(counts[1])
+        return {"idx": idx[:m].copy(), "ex": ex[:m].copy(),
+                "part_begin": part_begin[:parts + 1].copy(), "perfect": perfect.copy()}
+
     def bandwidth(self, nbr, label) -> dict:
         """B_f(G), C_BW and S_BW of the labelling label[old id] = new label."""
         nbr = np.ascontiguousarray(nbr, dtype=np.int32)
@@ -132,3 +154,7 @@ def am1_order(*a, **k):
 
 def bandwidth(*a, **k):
     return default().bandwidth(*a, **k)
+
+
+def am1_bounded(*a, **k):
+    return default().am1_bounded(*a, **k)

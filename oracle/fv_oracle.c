@@ -390,6 +390,56 @@ int oracle_bandwidth(int64_t n, const int32_t *nbr, const int32_t *label, int64_
 
 
 /*
+ * AM1's choice of the next node (section 4.2): the candidates are u(I), the
+ * neighbours of node(I) not yet in the part, in increasing id; for each,
+ * local_max is the largest imp(l) over its neighbours l in the part other
+ * than node(I); the first candidate whose local_max exceeds every earlier
+ * one (starting from 0) wins, else the first candidate.  pos[] holds part
+ * positions (-1 outside), uc[] and sv[] |u()| and s() by position;
+ * imp(l) = (size - 1 - l) + |u(l)| + s(l) for l >= I, 0 for l < I and for
+ * ghost positions (ghost may be NULL).
+ */
+static int64_t am1_candidate(const int32_t *nbr, int64_t vI, const int64_t *pos, int64_t I,
+                             int64_t size, const int64_t *uc, const int64_t *sv,
+                             const uint8_t *ghost)
+{
+    int32_t cnb[3];
+    const int cd = distinct_neighbours(nbr, vI, cnb);
+    int32_t cand[3] = {0, 0, 0};
+    int nc = 0;
+    for (int g = 0; g < cd; ++g)
+        if (pos[cnb[g]] < 0)
+            cand[nc++] = cnb[g];
+    for (int a1 = 1; a1 < nc; ++a1)
+        for (int b1 = a1; b1 > 0 && cand[b1 - 1] > cand[b1]; --b1) {
+            const int32_t t = cand[b1];
+            cand[b1] = cand[b1 - 1];
+            cand[b1 - 1] = t;
+        }
+    int64_t chosen = cand[0];
+    int64_t global_max = 0;
+    for (int c = 0; c < nc; ++c) {
+        int32_t knb[3];
+        const int kd = distinct_neighbours(nbr, cand[c], knb);
+        int64_t local_max = 0;
+        for (int g = 0; g < kd; ++g) {
+            const int64_t p = pos[knb[g]];
+            if (p < 0 || knb[g] == vI)
+                continue;
+            const int64_t imp =
+                (p < I || (ghost && ghost[p])) ? 0 : (size - 1 - p) + uc[p] + sv[p];
+            if (imp > local_max)
+                local_max = imp;
+        }
+        if (local_max > global_max) {
+            chosen = cand[c];
+            global_max = local_max;
+        }
+    }
+    return chosen;
+}
+
+/*
  * Amoeba1 (AM1) labelling of section 4.2, perm_out[new_label] = old id.
  *
  * A part P grows one node per step.  For the node at position i of P
@@ -466,41 +516,7 @@ int oracle_am1_order(int64_t n, const int32_t *nbr, int32_t *perm_out)
             if (I >= size)
                 break; /* component complete */
 
-            /* candidates: u(I) in increasing id */
-            const int64_t vI = perm_out[I];
-            int32_t cnb[3];
-            const int cd = distinct_neighbours(nbr, vI, cnb);
-            int32_t cand[3] = {0, 0, 0};
-            int nc = 0;
-            for (int g = 0; g < cd; ++g)
-                if (pos[cnb[g]] < 0)
-                    cand[nc++] = cnb[g];
-            for (int a1 = 1; a1 < nc; ++a1)
-                for (int b1 = a1; b1 > 0 && cand[b1 - 1] > cand[b1]; --b1) {
-                    const int32_t t = cand[b1];
-                    cand[b1] = cand[b1 - 1];
-                    cand[b1 - 1] = t;
-                }
-            int64_t chosen = cand[0];
-            int64_t global_max = 0;
-            for (int c = 0; c < nc; ++c) {
-                int32_t knb[3];
-                const int kd = distinct_neighbours(nbr, cand[c], knb);
-                int64_t local_max = 0;
-                for (int g = 0; g < kd; ++g) {
-                    const int64_t p = pos[knb[g]];
-                    if (p < 0 || knb[g] == vI)
-                        continue;
-                    const int64_t imp = p < I ? 0 : (size - 1 - p) + uc[p] + sv[p];
-                    if (imp > local_max)
-                        local_max = imp;
-                }
-                if (local_max > global_max) {
-                    chosen = cand[c];
-                    global_max = local_max;
-                }
-            }
-            next = chosen;
+            next = am1_candidate(nbr, perm_out[I], pos, I, size, uc, sv, NULL);
         }
         (void)first;
     }
@@ -511,4 +527,129 @@ int oracle_am1_order(int64_t n, const int32_t *nbr, int32_t *perm_out)
     free(queue);
     free(dist);
     return 0;
+}
+
+/*
+ * Access pattern with serial bandwidth at most `bound` (section 4.3): AM1
+ * parts that stop growing when the largest imp() from position I on exceeds
+ * the bound; a part's nodes before I are executed, the others only loaded
+ * (reloaded later), and vertices executed by earlier parts that a part needs
+ * again enter it as ghosts (u() empty, imp() = 0).  Each part starts at the
+ * George-Liu root of the not-yet-executed vertices, searched from the lowest
+ * such id.  Finalising a part: s* = min over positions k >= I of
+ * (k - s(k)); nodes before s* executed by this part are perfect (all their
+ * neighbours executed); nodes before I are executed.
+ * Outputs: idx[m] (vertex of each load), ex[m] (1 where the load executes
+ * it), part_begin[parts + 1], perfect[n]; counts[0] = m, counts[1] = parts.
+ * Readings: a part that would stop before executing anything keeps growing
+ * (cannot happen when bound > 3, the maximal degree); ghosts never become
+ * perfect (the flag is set only for nodes executed by the part, as the
+ * paper's finalisation states).
+ * Returns 0; -1 on a bad argument (bound <= 3) or allocation failure; -2 if
+ * the pattern or the part list exceeds its capacity.
+ */
+int oracle_am1_bounded(int64_t n, const int32_t *nbr, int64_t bound, int32_t *idx, uint8_t *ex,
+                       int64_t cap, int64_t *part_begin, int64_t part_cap, uint8_t *perfect,
+                       int64_t *counts)
+{
+    if (n <= 0 || !nbr || !idx || !ex || !part_begin || !perfect || !counts || bound <= 3 ||
+        cap <= 0 || part_cap <= 1)
+        return -1;
+    uint8_t *done = (uint8_t *)calloc((size_t)n, 1);      /* executed */
+    int64_t *pos = (int64_t *)malloc((size_t)n * sizeof(int64_t)); /* position in part, -1 */
+    int64_t *pv = (int64_t *)malloc((size_t)n * sizeof(int64_t));  /* vertex by position */
+    int64_t *sv = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *uc = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    uint8_t *ghost = (uint8_t *)malloc((size_t)n);
+    int64_t *queue = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *dist = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int rc = 0;
+    if (!done || !pos || !pv || !sv || !uc || !ghost || !queue || !dist) {
+        rc = -1;
+        goto out;
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        pos[v] = -1;
+        dist[v] = -1;
+        perfect[v] = 0;
+    }
+    int64_t m = 0, parts = 0, executed = 0, scan = 0;
+    part_begin[0] = 0;
+    while (executed < n) {
+        while (done[scan])
+            ++scan;
+        int64_t next = pseudo_peripheral_root(n, nbr, done, scan, queue, dist);
+        int64_t size = 0, I = 0;
+        for (;;) {
+            const int64_t p = size++;
+            pv[p] = next;
+            pos[next] = p;
+            ghost[p] = done[next];
+            int32_t nb[3];
+            const int d = distinct_neighbours(nbr, next, nb);
+            int64_t lo = p, free_count = 0;
+            for (int g = 0; g < d; ++g) {
+                const int64_t q = pos[nb[g]];
+                if (q >= 0) {
+                    if (q < lo)
+                        lo = q;
+                    if (!ghost[q])
+                        uc[q] -= 1;
+                } else {
+                    ++free_count;
+                }
+            }
+            sv[p] = ghost[p] ? 0 : p - lo;
+            uc[p] = ghost[p] ? 0 : free_count;
+            while (I < size && uc[I] == 0)
+                ++I;
+            if (I >= size)
+                break; /* everything reachable is complete */
+            int64_t max_imp = 0;
+            for (int64_t k = I; k < size; ++k) {
+                const int64_t imp = ghost[k] ? 0 : (size - 1 - k) + uc[k] + sv[k];
+                if (imp > max_imp)
+                    max_imp = imp;
+            }
+            if (max_imp > bound && I > 0)
+                break;
+            next = am1_candidate(nbr, pv[I], pos, I, size, uc, sv, ghost);
+        }
+        /* finalise the part */
+        int64_t sstar = size;
+        for (int64_t k = I; k < size; ++k)
+            if (k - sv[k] < sstar)
+                sstar = k - sv[k];
+        if (m + size > cap || parts + 2 > part_cap) {
+            rc = -2;
+            goto out;
+        }
+        for (int64_t k = 0; k < size; ++k) {
+            const int64_t v = pv[k];
+            if (k < sstar && !done[v])
+                perfect[v] = 1;
+            const int run = k < I && !ghost[k];
+            if (run) {
+                done[v] = 1;
+                ++executed;
+            }
+            idx[m] = (int32_t)v;
+            ex[m] = (uint8_t)run;
+            ++m;
+            pos[v] = -1;
+        }
+        part_begin[++parts] = m;
+    }
+    counts[0] = m;
+    counts[1] = parts;
+out:
+    free(done);
+    free(pos);
+    free(pv);
+    free(sv);
+    free(uc);
+    free(ghost);
+    free(queue);
+    free(dist);
+    return rc;
 }

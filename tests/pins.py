@@ -303,6 +303,64 @@ def pin_contact_advection(o, N=16, tf=1.0, u=0.6, v=0.8):
     return ok, f"phase {shift:.4f} vs {exact:.4f}, amplitude {amp:.3f}, u/v/p deviation {dev:.1e}"
 
 
+def pattern_sbw(nbr, pat):
+    """Serial bandwidth of an access pattern (section 4.3), with validity
+    checks: every vertex executed by exactly one load; an executed vertex's
+    neighbours all loaded in its part; per part, s/e = first/last position of
+    an executed vertex's closed neighbourhood (the load itself for a load
+    that only brings a ghost), S suffix minimum of s, E prefix maximum of e,
+    bandwidth max(E - S) (the section 4.1 definition).  Raises
+    AssertionError on an invalid pattern."""
+    n = nbr.shape[0]
+    idx, ex, pb = pat["idx"], pat["ex"], pat["part_begin"]
+    assert pb[0] == 0 and pb[-1] == len(idx), "part offsets"
+    counts = np.bincount(idx[ex == 1], minlength=n)
+    assert np.all(counts == 1), "every vertex executed exactly once"
+    sbw = 0
+    for p in range(len(pb) - 1):
+        a, b = int(pb[p]), int(pb[p + 1])
+        part = idx[a:b]
+        local = {int(v): t for t, v in enumerate(part)}
+        assert len(local) == b - a, "a vertex loaded twice in one part"
+        s = np.arange(b - a)
+        e = np.arange(b - a)
+        for t in range(b - a):
+            if ex[a + t]:
+                v = int(part[t])
+                ps = [t]
+                for w in {int(w) for w in nbr[v] if w != v}:
+                    assert w in local, f"neighbour {w} of executed {v} not in part {p}"
+                    ps.append(local[w])
+                s[t], e[t] = min(ps), max(ps)
+        S = np.minimum.accumulate(s[::-1])[::-1]
+        E = np.maximum.accumulate(e)
+        sbw = max(sbw, int(np.max(E - S)))
+    return sbw
+
+
+def pin_bounded_pattern(o, N=16):
+    """Section 4.3 on a shuffled mesh: at AM1's own bandwidth the pattern is
+    the AM1 order in one part; at half of it and at 6 the pattern is valid,
+    within the bound, and reloads some vertices."""
+    m = permute_mesh(periodic_mesh(N), random_permutation(2 * N * N, 2))
+    perm = o.am1_order(m.nbr)
+    lab = np.empty(m.n, dtype=np.int32)
+    lab[perm] = np.arange(m.n, dtype=np.int32)
+    full = o.bandwidth(m.nbr, lab)["S_BW"]
+    pat = o.am1_bounded(m.nbr, full)
+    if len(pat["part_begin"]) != 2 or not np.array_equal(pat["idx"], perm):
+        return False, "bound = AM1 bandwidth is not the AM1 order"
+    for bound in (full // 2, 6):
+        pat = o.am1_bounded(m.nbr, bound)
+        try:
+            got = pattern_sbw(m.nbr, pat)
+        except AssertionError as e:
+            return False, f"bound {bound}: {e}"
+        if got > bound or len(pat["idx"]) <= m.n:
+            return False, f"bound {bound}: bandwidth {got}, length {len(pat['idx'])}"
+    return True, f"AM1 bandwidth {full}"
+
+
 QUICK_PINS = [pin_golden_faces, pin_consistency, pin_xy_form, pin_antisymmetry, pin_conservation,
               pin_freestream, pin_translation, pin_stability, pin_contact_advection, pin_cm_golden,
-              pin_am1_golden, pin_bandwidth_golden]
+              pin_am1_golden, pin_bandwidth_golden, pin_bounded_pattern]

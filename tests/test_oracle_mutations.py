@@ -40,6 +40,10 @@ MUTATIONS = {
     "bandwidth not doubled": ("out[1] = 2 * B + 1;", "out[1] = B + 1;"),
     "AM1 ties move the candidate": ("if (local_max > global_max) {", "if (local_max >= global_max) {"),
     "AM1 scans from node(I) too": ("if (p < 0 || knb[g] == vI)", "if (p < 0)"),
+    "bounded pattern ignores its stop rule": ("if (max_imp > bound && I > 0)",
+                                              "if (max_imp > bound + 1000000 && I > 0)"),
+    "bounded pattern executes node(I) too": ("const int run = k < I && !ghost[k];",
+                                             "const int run = k <= I && !ghost[k];"),
 }
 
 
