@@ -78,7 +78,20 @@ def cpu_baseline(m, U0, dt, fv_steps: int, sample_steps: int) -> dict:
     t0 = time.perf_counter()
     oracle.step(mc.nbr, mc.nrm, mc.area, Uc, dt, sample_steps)
     t_step = (time.perf_counter() - t0) / sample_steps
+    # the same steps on the random order: the CPU side of the renumbering
+    # comparison (section 7.2 measures 3-15 % on one core)
+    rnd = max(1, sample_steps // 4)
+    t0 = time.perf_counter()
+    oracle.step(m.nbr, m.nrm, m.area, U0, dt, rnd)
+    t_rnd = (time.perf_counter() - t0) / rnd
     job = t_cm + fv_steps * t_step
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                             "")
+    except OSError:
+        pass
     return {
         "value": m.n * fv_steps / job,
         "unit": "cell-updates/s",
@@ -88,6 +101,9 @@ def cpu_baseline(m, U0, dt, fv_steps: int, sample_steps: int) -> dict:
                    f"{sample_steps} oracle steps on the renumbered mesh ({t_step:.3f} s/step), "
                    f"scaled to the {fv_steps}-step job"),
         "step_only_value": m.n / t_step,
+        "random_order_s_per_step": t_rnd,
+        "renumbered_s_per_step": t_step,
+        "cpu_model": cpu_model,
     }
 
 
@@ -241,7 +257,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1, help="untimed jobs")
     ap.add_argument("--fv-steps", type=int, default=1000, help="time steps per job")
     ap.add_argument("--N", type=int, default=1024, help="quads per side")
-    ap.add_argument("--cpu-sample-steps", type=int, default=20)
+    ap.add_argument("--cpu-sample-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-random", action="store_true",
                     help="skip timing the step on the random (not renumbered) order")
