@@ -276,6 +276,78 @@ def compare(params, N: int, r: int, seeds, steps: int, cfl: float = 0.8,
     return res
 
 
+def compare_levels(params, N: int, seeds, horizons, cfl: float = 0.8) -> dict:
+    """Plain and corrected N x N solvers, the plain 2N x 2N solver and a plain
+    4N x 4N reference, all from the reference's initial state restricted to
+    each mesh; L2 density errors against the reference restricted to N x N
+    after each number of coarse steps in `horizons` (2 and 4 substeps per
+    coarse step on the finer meshes).  Answers whether the corrected coarse
+    solver reaches the 2N solver's accuracy."""
+    import torch
+
+    from fvgen.nested import nested_pair
+
+    c, ref, idx4, w4 = nested_pair(N, 4)
+    _log(f"meshes {N}x{N} and {4 * N}x{4 * N} built")
+    mid, _, idx2f, w2f = nested_pair(2 * N, 2)
+    _, _, idx2, w2 = nested_pair(N, 2)
+    _log(f"mesh {2 * N}x{2 * N} built")
+    h = 10.0 / N
+    dt_r = mesh_dt(ref, cfl)
+    R4 = Restriction(idx4, w4, ref.n, 1, torch)  # reference -> coarse
+    Rrm = Restriction(idx2f, w2f, ref.n, 1, torch)  # reference -> 2N
+    R2 = Restriction(idx2, w2, mid.n, 1, torch)  # 2N -> coarse
+    del idx4, w4, idx2f, w2f, idx2, w2
+    area = torch.tensor(c.area, device="cuda")
+    A = float(c.area.sum())
+    horizons = sorted(int(k) for k in horizons)
+    out = {"N": N, "horizons": horizons, "dt_coarse": 4 * dt_r, "flows": []}
+    rs = Solver(ref.nbr, ref.nrm, ref.area)
+    ms = Solver(mid.nbr, mid.nrm, mid.area)
+    cs = Solver(c.nbr, c.nrm, c.area)
+    for s in (rs, ms, cs):
+        s.renumber()
+
+    def err(U, T):
+        return float(torch.sqrt(density_error(torch, U, T, area) / A))
+
+    def run(solver, U0, sub, dt, restrict, p=None):
+        """restricted (coarse-mesh) states after each horizon"""
+        if solver is cs:
+            cs.set_correction(p)
+        solver.upload_state(U0)
+        done, states = 0, []
+        for k in horizons:
+            solver.step(sub * (k - done), dt)
+            done = k
+            U = solver.download_device()
+            states.append(restrict(U).clone() if restrict else U)
+        return states
+
+    try:
+        for seed in seeds:
+            rs.upload_state(flows(ref, h, [seed])[0])
+            _log(f"seed {seed}: reference state uploaded")
+            U0r = rs.download_device()
+            U0m, U0c = Rrm(U0r).clone(), R4(U0r).clone()
+            T = run(rs, U0r, 4, dt_r, R4)
+            Em = run(ms, U0m, 2, 2 * dt_r, R2)
+            Ep = run(cs, U0c, 1, 4 * dt_r, None)
+            Ec = run(cs, U0c, 1, 4 * dt_r, None, params)
+            for q, k in enumerate(horizons):
+                rec = {"seed": int(seed), "steps": k, "coarse_plain": err(Ep[q], T[q]),
+                       "coarse_corrected": err(Ec[q], T[q]), "fine_plain": err(Em[q], T[q])}
+                out["flows"].append(rec)
+                _log(f"N={N} seed {seed} {k} steps, L2 density error vs the {4 * N}x{4 * N} "
+                     f"reference: coarse plain {rec['coarse_plain']:.3e}, coarse corrected "
+                     f"{rec['coarse_corrected']:.3e}, {2 * N}x{2 * N} plain "
+                     f"{rec['fine_plain']:.3e}")
+    finally:
+        for s in (rs, ms, cs):
+            s.close()
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
