@@ -143,10 +143,11 @@ __device__ __forceinline__ void write_features(short *dst, const Side &L, const 
                          (float)geo_a,                 (float)geo_c};
     const s2 p0 = bf16x2(f[0], f[1]), p1 = bf16x2(f[2], f[3]), p2 = bf16x2(f[4], f[5]);
     const s2 p3 = bf16x2(f[6], f[7]), p4 = bf16x2(f[8], f[9]), p5 = bf16x2(f[10], f[11]);
-    const s8 lo = {p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
-    const s8 hi = {p4[0], p4[1], p5[0], p5[1], kBf16One, 0, 0, 0};
-    *reinterpret_cast<s8 *>(dst) = lo;
-    *reinterpret_cast<s8 *>(dst + 8) = hi;
+    s4 *d = reinterpret_cast<s4 *>(dst);  // 8-byte aligned rows
+    d[0] = s4{p0[0], p0[1], p1[0], p1[1]};
+    d[1] = s4{p2[0], p2[1], p3[0], p3[1]};
+    d[2] = s4{p4[0], p4[1], p5[0], p5[1]};
+    d[3] = s4{kBf16One, 0, 0, 0};
 }
 
 // R(e) y in float64
@@ -268,8 +269,8 @@ __global__ __launch_bounds__(kBlock, 3) void fv_step_learned_kernel(
     const double *__restrict__ inv_area, const short *__restrict__ frags,
     const float *__restrict__ bias, double gamma)
 {
-    __shared__ short Xs[kWaves][64 * kXStride];
-    __shared__ float Ys[kWaves][64 * 8];
+    __shared__ __attribute__((aligned(16))) short Xs[kWaves][64 * kXStride];
+    __shared__ __attribute__((aligned(16))) float Ys[kWaves][64 * 8];
     __shared__ __attribute__((aligned(16))) short Wl[kCorrFragShorts];
     __shared__ __attribute__((aligned(16))) float Bl[kCorrBias];
 
@@ -325,11 +326,10 @@ __global__ __launch_bounds__(kBlock, 3) void fv_step_learned_kernel(
                 write_features(xs + 16, R, L, -ex, -ey, 0.5 * len * len * (aj + ai),
                                0.5 * len * (cj + ci));
             } else {
-                const s8 z = {0, 0, 0, 0, 0, 0, 0, 0};
-                *reinterpret_cast<s8 *>(xs) = z;
-                *reinterpret_cast<s8 *>(xs + 8) = z;
-                *reinterpret_cast<s8 *>(xs + 16) = z;
-                *reinterpret_cast<s8 *>(xs + 24) = z;
+                s4 *d = reinterpret_cast<s4 *>(xs);
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    d[q] = s4{0, 0, 0, 0};
             }
             wave_sync();
             mlp_rows(Wl, Bl, X, Y, lane);
@@ -544,9 +544,9 @@ __global__ __launch_bounds__(kBlock) void fv_adjoint_learned_kernel(
     const double *__restrict__ area, double dt, double gamma, const short *__restrict__ afrags,
     const float *__restrict__ bias, float *__restrict__ partial)
 {
-    __shared__ short Xs[kWaves][64 * kXStride];
-    __shared__ short Ws[kWaves][64 * kWcStride];
-    __shared__ float Ds[kWaves][64 * 8];
+    __shared__ __attribute__((aligned(16))) short Xs[kWaves][64 * kXStride];
+    __shared__ __attribute__((aligned(16))) short Ws[kWaves][64 * kWcStride];
+    __shared__ __attribute__((aligned(16))) float Ds[kWaves][64 * 8];
     __shared__ __attribute__((aligned(16))) short Af[kCorrAdjFragShorts];
     __shared__ __attribute__((aligned(16))) float Bl[kCorrBias];
 
@@ -622,12 +622,11 @@ __global__ __launch_bounds__(kBlock) void fv_adjoint_learned_kernel(
                 *reinterpret_cast<s8 *>(Wc + lane * kWcStride) =
                     s8{a01[0], a01[1], a23[0], a23[1], b01[0], b01[1], b23[0], b23[1]};
             } else {
-                const s8 z = {0, 0, 0, 0, 0, 0, 0, 0};
-                *reinterpret_cast<s8 *>(xs) = z;
-                *reinterpret_cast<s8 *>(xs + 8) = z;
-                *reinterpret_cast<s8 *>(xs + 16) = z;
-                *reinterpret_cast<s8 *>(xs + 24) = z;
-                *reinterpret_cast<s8 *>(Wc + lane * kWcStride) = z;
+                s4 *d = reinterpret_cast<s4 *>(xs);
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    d[q] = s4{0, 0, 0, 0};
+                *reinterpret_cast<s8 *>(Wc + lane * kWcStride) = s8{0, 0, 0, 0, 0, 0, 0, 0};
             }
             wave_sync();
             mlp_adjoint_rows(Af, Bl, X, Wc, DX, acc, lane);
