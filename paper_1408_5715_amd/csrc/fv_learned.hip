@@ -225,7 +225,7 @@ __device__ __forceinline__ void mlp_rows(const short *Wl, const float *Bl, const
     const int quad = lane >> 4, col = lane & 15;
     Mlp W;
     load_mlp(W, Wl, Bl, lane);
-#pragma unroll 1
+#pragma unroll 2
     for (int g = 0; g < 8; ++g) {
         const int cell = 16 * (g >> 1) + col, r = g & 1;
         const s4 xb = *reinterpret_cast<const s4 *>(&X[cell * kXStride + 16 * r + 4 * quad]);
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kBlock, 3) void fv_step_learned_kernel(
         }
         const Side L = side_of(Ui, gamma);
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll 1
+#pragma unroll
         for (int f = 0; f < 3; ++f) {
             double len = 1.0, ex = 1.0, ey = 0.0;
             if (live) {
