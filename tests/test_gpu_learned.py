@@ -108,3 +108,67 @@ def test_launch_shapes_and_batches_bitwise(torch):
         s.close()
     assert np.array_equal(got[a.n:], ref)
     assert np.array_equal(got[:a.n], run(a, Ua, dta, 20, p, fv.FV_ORDER_CM))
+
+
+@pytest.mark.parametrize("closed", [True, False])
+def test_layout_variants(torch, closed):
+    """The four geometry layouts of the corrected step (16-bit offsets or
+    32-bit ids, derived or stored third normal) give the same bits for runs
+    that differ only in the cell order, and match the CPU reference."""
+    from test_gpu_step import open_normals
+
+    N = 160  # a random order has neighbour offsets beyond 16 bits, CM's do not
+    m, U0, dt = vortex_case(N)
+    nrm = m.nrm if closed else open_normals(m)
+    p = learned_ref.random_params(4)
+    a = run(m, U0, dt, 3, p, fv.FV_ORDER_IDENTITY, nrm=nrm)
+    b = run(m, U0, dt, 3, p, fv.FV_ORDER_CM, nrm=nrm)
+    assert np.array_equal(a, b)
+    plain = run(m, U0, dt, 3, None, fv.FV_ORDER_CM, nrm=nrm)
+    M = torch_ref.Mesh(m.nbr, nrm, m.area)
+    Ur, Up = _torch.from_numpy(U0), _torch.from_numpy(U0)
+    for _ in range(3):
+        Ur = learned_ref.corrected_step(M, Ur, dt, p)
+        Up = torch_ref.step(M, Up, dt)
+    d_ref = (Ur - Up).numpy()
+    err = np.max(np.abs((b - plain) - d_ref)) / np.max(np.abs(d_ref))
+    log(f"layout closed={closed}: correction effect vs reference {err:.2e}")
+    assert err <= 2e-2
+
+
+def test_graph_replays_and_tiny_meshes(torch):
+    """A captured graph of corrected steps replays to the eager bits (several
+    replays, eager work in between), and the smallest meshes (2 x 2 quads,
+    where a cell meets the same neighbour across two faces) match the CPU
+    reference."""
+    m, U0, dt = vortex_case(20)
+    p = learned_ref.random_params(6)
+    eager = run(m, U0, dt, 12, p, fv.FV_ORDER_CM)
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        s.renumber(fv.FV_ORDER_CM)
+        s.set_correction(p)
+        s.set_launch(256, 0, True)
+        for rep in range(3):
+            s.upload_state(U0)
+            s.step(12, dt)
+            got = s.download()
+            assert np.array_equal(got, eager), rep
+            s.set_launch(256, 0, False)
+            s.step(1, dt)  # eager work between replays
+            s.set_launch(256, 0, True)
+    finally:
+        s.close()
+    for N in (2, 3):
+        m, U0, dt = vortex_case(N)
+        got = run(m, U0, dt, 4, p, fv.FV_ORDER_CM)
+        plain = run(m, U0, dt, 4, None, fv.FV_ORDER_CM)
+        M = torch_ref.Mesh(m.nbr, m.nrm, m.area)
+        Ur, Up = _torch.from_numpy(U0), _torch.from_numpy(U0)
+        for _ in range(4):
+            Ur = learned_ref.corrected_step(M, Ur, dt, p)
+            Up = torch_ref.step(M, Up, dt)
+        d_ref = (Ur - Up).numpy()
+        err = np.max(np.abs((got - plain) - d_ref)) / np.max(np.abs(d_ref))
+        log(f"N={N}: correction effect vs reference {err:.2e}")
+        assert err <= 2e-2
