@@ -126,7 +126,7 @@ struct PassLds {
 // One breadth-first Cuthill-McKee labelling of the component of `root`,
 // labels from `base`: rec[v].w = label, perm[label] = v.  rec[v].w must be
 // -1 for every cell of the component.  Called by all threads of the block.
-__device__ PassResult cm_pass(int4 *__restrict__ rec, int32_t root, int32_t base,
+__device__ __forceinline__ PassResult cm_pass(int4 *__restrict__ rec, int32_t root, int32_t base,
                               int32_t *__restrict__ perm, PassLds &lds)
 {
     int4 (&frontier)[2][kFrontierCap] = lds.frontier;
