@@ -18,19 +18,20 @@
 // MFMA mapping (wave64).  Weights are the A operand (rows = output units, 16
 // per tile) and 16 MLP rows (faces) the B operand (columns).  The first
 // layer's bias is a weight row against a constant-1 feature (so it is
-// bfloat16 like the weights); the other biases are the accumulator input.  The accumulator of an output tile holds, in lane l,
-// units 4 (l / 16) + i of face column l % 16.  Two such tiles (units 32 s +
-// 4 (l / 16) + i and 32 s + 16 + 4 (l / 16) + i) form lane l's eight K values
-// of the next layer's v_mfma_f32_16x16x32_bf16 B operand; the weight
-// fragments are packed in that K order, so layers chain in registers.  Per
-// 16 rows: 4 (16x16x16, K = 12 padded to 16) + 8 + 2 (16x16x32) MFMAs.
+// bfloat16 like the weights); the other biases are the accumulator input.
+// The accumulator of an output tile holds, in lane l, units 4 (l / 16) + i of
+// face column l % 16.  Two such tiles (units 32 s + 4 (l / 16) + i and
+// 32 s + 16 + 4 (l / 16) + i) form lane l's eight K values of the next
+// layer's v_mfma_f32_16x16x32_bf16 B operand; the weight fragments are packed
+// in that K order, so layers chain in registers.  Per 16 rows: 4 (16x16x16,
+// K = 12 padded to 16) + 8 + 2 (16x16x32) MFMAs.
 //
 // Work split: a wave owns 64 cells (lane = cell).  For each face slot f it
 // computes, per cell, the Lax-Friedrichs flux and the two feature rows in
 // float64, passes the 128 rows through LDS to the MLP, and adds the rotated
 // outputs back.  Waves only exchange data with themselves (wave-scope
-// synchronisation); weight fragments stay in registers for the whole
-// persistent workgroup.
+// synchronisation).  The packed weights are copied to LDS once per
+// persistent workgroup and read into registers for each face slot's MLP.
 
 #include <cstring>
 
