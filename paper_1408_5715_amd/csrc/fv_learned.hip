@@ -131,24 +131,61 @@ __device__ __forceinline__ Side side_of(const double4 &U, double gamma)
 
 // Features of the row (L, R, unit normal e) as 16 bfloat16: the 12 features
 // (float64 -> float32 -> bfloat16, each rounding to nearest even), then a
-// constant 1 that multiplies the first layer's bias, then zeros.
-__device__ __forceinline__ void write_features(short *dst, const Side &L, const Side &R, double ex,
-                                               double ey, double geo_a, double geo_c)
+// constant 1 that multiplies the first layer's bias, then zeros.  The 12 are
+// returned as six packed pairs (element 0 in the low half): (rho_L, un_L),
+// (ut_L, p_L), (rho_R, un_R), (ut_R, p_R), (e_x, e_y), (geo_a, geo_c).
+struct FeaturePairs {
+    unsigned p[6];
+};
+
+__device__ __forceinline__ unsigned pack_pair(float a, float b)
+{
+    const s2 v = bf16x2(a, b);
+    return (unsigned)(unsigned short)v[0] | ((unsigned)(unsigned short)v[1] << 16);
+}
+
+__device__ __forceinline__ FeaturePairs features(const Side &L, const Side &R, double ex, double ey,
+                                                 double geo_a, double geo_c)
 {
     const double tx = -ey, ty = ex;
-    const float f[12] = {(float)(L.rho - 1.0),         (float)(L.u * ex + L.v * ey),
-                         (float)(L.u * tx + L.v * ty), (float)(L.p - 1.0),
-                         (float)(R.rho - 1.0),         (float)(R.u * ex + R.v * ey),
-                         (float)(R.u * tx + R.v * ty), (float)(R.p - 1.0),
-                         (float)ex,                    (float)ey,
-                         (float)geo_a,                 (float)geo_c};
-    const s2 p0 = bf16x2(f[0], f[1]), p1 = bf16x2(f[2], f[3]), p2 = bf16x2(f[4], f[5]);
-    const s2 p3 = bf16x2(f[6], f[7]), p4 = bf16x2(f[8], f[9]), p5 = bf16x2(f[10], f[11]);
-    s4 *d = reinterpret_cast<s4 *>(dst);  // 8-byte aligned rows
-    d[0] = s4{p0[0], p0[1], p1[0], p1[1]};
-    d[1] = s4{p2[0], p2[1], p3[0], p3[1]};
-    d[2] = s4{p4[0], p4[1], p5[0], p5[1]};
-    d[3] = s4{kBf16One, 0, 0, 0};
+    FeaturePairs f;
+    f.p[0] = pack_pair((float)(L.rho - 1.0), (float)(L.u * ex + L.v * ey));
+    f.p[1] = pack_pair((float)(L.u * tx + L.v * ty), (float)(L.p - 1.0));
+    f.p[2] = pack_pair((float)(R.rho - 1.0), (float)(R.u * ex + R.v * ey));
+    f.p[3] = pack_pair((float)(R.u * tx + R.v * ty), (float)(R.p - 1.0));
+    f.p[4] = pack_pair((float)ex, (float)ey);
+    f.p[5] = pack_pair((float)geo_a, (float)geo_c);
+    return f;
+}
+
+// One 16-value row (8-byte aligned) from six pairs: two 8-byte stores for the
+// features, one for (e, geo), one for (1, 0, 0, 0).
+__device__ __forceinline__ void store_row(short *dst, unsigned q0, unsigned q1, unsigned q2,
+                                          unsigned q3, unsigned q4, unsigned q5)
+{
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    u2 *d = reinterpret_cast<u2 *>(dst);
+    d[0] = u2{q0, q1};
+    d[1] = u2{q2, q3};
+    d[2] = u2{q4, q5};
+    d[3] = u2{(unsigned)(unsigned short)kBf16One, 0u};
+}
+
+// The two rows of a face: x(L, R, e) at dstA and x(R, L, -e) at dstB.  The
+// second is the first with the two cells' halves swapped and the signs of
+// the normal and tangential velocities and of e flipped: each of those
+// float64 values is the exact negation of its counterpart, and both roundings
+// (to float32, then to bfloat16, nearest even) commute with negation, so
+// flipping sign bits gives the patterns features(R, L, -e) would produce
+// (up to the sign of an exact zero, which no sum in the MLP can observe).
+__device__ __forceinline__ void write_feature_pair(short *dstA, short *dstB, const Side &L,
+                                                   const Side &R, double ex, double ey,
+                                                   double geo_a, double geo_c)
+{
+    const FeaturePairs f = features(L, R, ex, ey, geo_a, geo_c);
+    store_row(dstA, f.p[0], f.p[1], f.p[2], f.p[3], f.p[4], f.p[5]);
+    store_row(dstB, f.p[2] ^ 0x80000000u, f.p[3] ^ 0x00008000u, f.p[0] ^ 0x80000000u,
+              f.p[1] ^ 0x00008000u, f.p[4] ^ 0x80008000u, f.p[5]);
 }
 
 // R(e) y in float64
@@ -322,10 +359,8 @@ __global__ __launch_bounds__(kBlock, 3) void fv_step_learned_kernel(
                 a2 += 0.5 * (Ui.z * VL + Uj.z * VR + pp * ny) - 0.5 * s * (Uj.z - Ui.z);
                 a3 += 0.5 * ((Ui.w + L.p) * VL + (Uj.w + R.p) * VR) - 0.5 * s * (Uj.w - Ui.w);
                 const double aj = inv_area[j], cj = coef[j];
-                write_features(xs, L, R, ex, ey, 0.5 * len * len * (ai + aj),
-                               0.5 * len * (ci + cj));
-                write_features(xs + 16, R, L, -ex, -ey, 0.5 * len * len * (aj + ai),
-                               0.5 * len * (cj + ci));
+                write_feature_pair(xs, xs + 16, L, R, ex, ey, 0.5 * len * len * (ai + aj),
+                                   0.5 * len * (ci + cj));
             } else {
                 s4 *d = reinterpret_cast<s4 *>(xs);
 #pragma unroll
@@ -611,10 +646,8 @@ __global__ __launch_bounds__(kBlock) void fv_adjoint_learned_kernel(
                 const double rl = recip(len);
                 ex = nx * rl;
                 ey = ny * rl;
-                write_features(xs, L, R, ex, ey, 0.5 * len * len * (ak + aj),
-                               0.5 * len * (ck + cj));
-                write_features(xs + 16, R, L, -ex, -ey, 0.5 * len * len * (aj + ak),
-                               0.5 * len * (cj + ck));
+                write_feature_pair(xs, xs + 16, L, R, ex, ey, 0.5 * len * len * (ak + aj),
+                                   0.5 * len * (ck + cj));
                 const double ve = v[1] * ex + v[2] * ey, vt = -v[1] * ey + v[2] * ex;
                 const s2 a01 = bf16x2((float)(len * v[0]), (float)(len * ve));
                 const s2 a23 = bf16x2((float)(len * vt), (float)(len * v[3]));
