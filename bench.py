@@ -49,7 +49,7 @@ STEP_SOURCE = os.path.join(ROOT, "paper_1408_5715_amd", "csrc", "fv_step.hip")
 MEASURED_TRAFFIC = {
     "source_sha": "6c72436b4da61f8a93c3d89355655ecf1f9072f5330eb758d42101231a9436de",
     "cells": 2097152,
-    "bytes_per_launch": 235954049,  # fetch 168,845,996 + write 67,108,053
+    "bytes_per_launch": 235953889,  # fetch 168,846,284 + write 67,107,605
 }
 
 

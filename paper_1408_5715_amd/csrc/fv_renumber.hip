@@ -14,23 +14,25 @@
 // children, and a block-wide exclusive scan of the child counts gives every
 // child its label.  The result equals the sequential order exactly.
 //
-// One workgroup of 1024 threads labels a whole mesh in one launch (all
-// levels, the pseudo-peripheral search and every component): levels are a
-// few thousand cells wide, so the work per level is small, and a grid-wide
-// barrier per level (which on this chip means writing back and invalidating
-// per-XCD L2 caches) would cost more than it saves.  A batch of independent
-// meshes runs one such workgroup per mesh, side by side.
-// Every wave leaves the level loop on the same block-uniform condition (an
-// empty next level).
+// One workgroup of 1024 threads labels a whole mesh (all levels, the
+// pseudo-peripheral search and every component), in two launches around a
+// grid-wide renaming of the graph: levels are a few thousand cells wide, so
+// the work per level is small, and a grid-wide barrier per level (which on
+// this chip means writing back and invalidating per-XCD L2 caches) would cost
+// more than it saves.  A batch of independent meshes runs one such workgroup
+// per mesh, side by side.  Every wave leaves the level loop on the same
+// block-uniform condition (an empty next level).
 //
 // The graph is read as 16-byte records: three neighbours and the cell's
 // label (-1 while unlabelled), so one cache-line fetch answers both "is w
 // labelled" and "who are w's neighbours".  Frontier cells carry their
-// neighbour lists in LDS (fetched when they were discovered).  One CU runs
-// the whole labelling, and its cost is set by the number of scattered lane
-// requests per cell, so loads are issued only by the lanes that need them
-// (about 5.6 per frontier cell: three neighbour records and the labels of
-// the other neighbours of unlabelled cells).
+// neighbour lists in LDS (fetched when they were discovered), with a mask of
+// the neighbours already known to be labelled then (the owner, and any whose
+// label the discovery read); their records are not fetched again, since a
+// labelled cell is never a child.  One CU runs the whole labelling, and its
+// cost is set by the latency of scattered loads, so loads are issued only by
+// the lanes that need them (the records of the neighbours not known to be
+// labelled, and the labels of the other neighbours of unlabelled cells).
 
 #include <climits>
 
@@ -41,8 +43,10 @@ namespace {
 
 constexpr int kCmThreads = 1024;
 constexpr int kCmWaves = kCmThreads / 64;
-constexpr int kFrontierCap = 4096;  // frontier entries held in LDS per buffer (2 x 64 KiB)
+constexpr int kFrontierCap = 4096;  // frontier entries held in LDS per buffer (2 x 64 KiB + masks)
 constexpr int kPer = 3;             // frontier cells per thread and sweep
+
+typedef int i4v __attribute__((ext_vector_type(4)));  // a record as one register tuple
 
 // Block-wide exclusive scan over 1024 threads; *total receives the sum.
 __device__ __forceinline__ int block_exclusive_scan(int x, int *sh, int *total)
@@ -119,9 +123,175 @@ struct PassResult {
 // LDS of one labelling pass.
 struct PassLds {
     int4 frontier[2][kFrontierCap];  // (cell, nb_0, nb_1, nb_2), in label order
+    unsigned char known[2][kFrontierCap];  // bit f: nb_f was labelled at discovery
     int scan[2 * kCmWaves + 1];
     unsigned long long minv[kCmWaves];
 };
+
+// One sweep of a level [a, b) of a labelling pass: the frontier positions
+// [c0, c0 + span), P per thread (thread tid takes the contiguous run
+// [tid * P, tid * P + P), so the scan of per-thread child counts keeps the
+// label order).  Children are labelled from b + produced on.  Waves with no
+// position skip the work (P is the smallest count that covers the sweep, so
+// no thread does empty slots beyond its wave's share).  Returns the number of
+// children (block-uniform).  Called by all threads of the block.
+template <int P>
+__device__ __forceinline__ int cm_sweep(int4 *__restrict__ rec, int32_t *__restrict__ perm,
+                                        PassLds &lds, int cur, int a, int b, int c0, int span,
+                                        int produced)
+{
+    int4 (&frontier)[2][kFrontierCap] = lds.frontier;
+    unsigned char (&known)[2][kFrontierCap] = lds.known;
+    int32_t *label = reinterpret_cast<int32_t *>(rec);  // label of cell v: label[4 v + 3]
+    const int tid = threadIdx.x;
+    const int first = tid * P;
+    const bool wave_busy = (tid & ~63) * P < span;  // the wave's first thread has a position
+
+    // kept across the scan: per candidate slot, (child, rank among the cell's
+    // children, mask of its neighbours known to be labelled) packed in one int
+    int w[P][3], x[P][3][3], info[P][3], nk[P];
+    int total = 0;
+    if (wave_busy) {
+        int v[P];
+        unsigned kn[P];
+        bool ok[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int t = first + k;
+            ok[k] = t < span;
+            const int ft = c0 + t;
+            const int slot = (ok[k] && ft < kFrontierCap) ? ft : 0;
+            // the LDS entry is made opaque so that the compiler keeps it an
+            // LDS read instead of merging it with the global read below into
+            // one generic (flat) load, whose wait would hold back every
+            // global load after it
+            i4v e = reinterpret_cast<const i4v *>(frontier[cur])[slot];
+            unsigned kb = known[cur][slot];
+            asm volatile("" : "+v"(e), "+v"(kb));
+            kn[k] = kb;
+            if (ok[k] && ft >= kFrontierCap) {
+                const int c = perm[a + ft];
+                const int4 r = rec[c];
+                e = i4v{c, r.x, r.y, r.z};
+                kn[k] = 0;
+            }
+            v[k] = e[0];
+            w[k][0] = e[1];
+            w[k][1] = e[2];
+            w[k][2] = e[3];
+        }
+        // records of the neighbours not known to be labelled: their label and
+        // their neighbours (a skipped one reads as labelled, w = 0).  The
+        // empty asm statements after the loop make each record's value opaque
+        // where it is used, so the compiler cannot move the uses into the
+        // branch that loads it (which would wait for each load before issuing
+        // the next): all loads are in flight together.
+        const i4v *recv = reinterpret_cast<const i4v *>(rec);
+        i4v rw[P][3];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const bool fetch = ok[k] && !((kn[k] >> f) & 1u);
+                rw[k][f] = i4v{0, 0, 0, 0};
+                if (fetch)
+                    rw[k][f] = recv[w[k][f]];
+            }
+        }
+        int lw[P][3];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                i4v r = rw[k][f];
+                asm volatile("" : "+v"(r));
+                x[k][f][0] = r[0];
+                x[k][f][1] = r[1];
+                x[k][f][2] = r[2];
+                lw[k][f] = r[3];
+            }
+        }
+        // an unlabelled neighbour ww is a child of v[k] when v[k] has the
+        // smallest label among ww's neighbours inside the frontier; the labels
+        // of ww's other neighbours are read for candidates only
+        bool cand[P][3];
+        int lx[P][3][3];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const int ww = w[k][f];
+                cand[k][f] = ok[k] && ww != v[k] && !(f >= 1 && w[k][0] == ww) &&
+                             !(f == 2 && w[k][1] == ww) && lw[k][f] == -1;
+#pragma unroll
+                for (int g = 0; g < 3; ++g) {
+                    const int xg = x[k][f][g];
+                    lx[k][f][g] = (cand[k][f] && xg != v[k]) ? label[4 * xg + 3] : -1;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int lv = a + c0 + first + k;
+            bool child[3];
+            int kdeg[3];
+            nk[k] = 0;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                int owner = INT_MAX;
+#pragma unroll
+                for (int g = 0; g < 3; ++g) {
+                    const int l = x[k][f][g] == v[k] ? lv : lx[k][f][g];
+                    if (l >= a && l < b && l < owner)
+                        owner = l;
+                }
+                child[f] = cand[k][f] && owner == lv;
+                kdeg[f] = degree_of(w[k][f], x[k][f][0], x[k][f][1], x[k][f][2]);
+                nk[k] += child[f];
+            }
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                int rank = 0;
+                unsigned m = 0;
+#pragma unroll
+                for (int g = 0; g < 3; ++g) {
+                    const bool before =
+                        kdeg[g] < kdeg[f] || (kdeg[g] == kdeg[f] && w[k][g] < w[k][f]);
+                    rank += (g != f && child[g] && before);
+                    // c's neighbours known to be labelled: its owner and those
+                    // whose label was read above
+                    m |= (unsigned)(x[k][f][g] == v[k] || lx[k][f][g] != -1) << g;
+                }
+                info[k][f] = child[f] ? (int)(1u | (unsigned)rank << 1 | m << 3) : 0;
+            }
+            total += nk[k];
+        }
+    }
+    int sweep_total;
+    int pos = produced + block_exclusive_scan(total, lds.scan, &sweep_total);
+    if (wave_busy) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const int in = info[k][f];
+                if (in & 1) {
+                    const int p = pos + ((in >> 1) & 3);
+                    const int lab = b + p;
+                    const int c = w[k][f];
+                    label[4 * c + 3] = lab;
+                    perm[lab] = c;
+                    if (p < kFrontierCap) {
+                        frontier[cur ^ 1][p] = make_int4(c, x[k][f][0], x[k][f][1], x[k][f][2]);
+                        known[cur ^ 1][p] = (unsigned char)(in >> 3);
+                    }
+                }
+            }
+            pos += nk[k];
+        }
+    }
+    return sweep_total;
+}
 
 // One breadth-first Cuthill-McKee labelling of the component of `root`,
 // labels from `base`: rec[v].w = label, perm[label] = v.  rec[v].w must be
@@ -130,6 +300,7 @@ __device__ __forceinline__ PassResult cm_pass(int4 *__restrict__ rec, int32_t ro
                               int32_t *__restrict__ perm, PassLds &lds)
 {
     int4 (&frontier)[2][kFrontierCap] = lds.frontier;
+    unsigned char (&known)[2][kFrontierCap] = lds.known;
     int *scan_sh = lds.scan;
     unsigned long long *min_sh = lds.minv;
 
@@ -141,6 +312,7 @@ __device__ __forceinline__ PassResult cm_pass(int4 *__restrict__ rec, int32_t ro
         label[4 * root + 3] = base;
         perm[base] = root;
         frontier[0][0] = make_int4(root, r.x, r.y, r.z);
+        known[0][0] = 0;
     }
     __threadfence_block();
     __syncthreads();
@@ -151,112 +323,18 @@ __device__ __forceinline__ PassResult cm_pass(int4 *__restrict__ rec, int32_t ro
     for (;;) {
         const int F = b - a;
         int produced = 0;  // children labelled so far in this level (block-uniform)
-        // One sweep covers up to kCmThreads * kPer frontier cells; thread tid
-        // takes the contiguous run [tid * per, tid * per + per) of the sweep,
-        // so the scan of per-thread child counts keeps the label order.
+        // One sweep covers up to kCmThreads * kPer frontier cells, with the
+        // smallest per-thread count that covers them.
         for (int c0 = 0; c0 < F; c0 += kCmThreads * kPer) {
             const int span = min(F - c0, kCmThreads * kPer);
             const int per = (span + kCmThreads - 1) / kCmThreads;
-            const int first = tid * per;
-
-            int v[kPer], w[kPer][3];
-            bool ok[kPer];
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int t = first + k;
-                ok[k] = k < per && t < span;
-                const int ft = c0 + t;
-                int4 e = frontier[cur][(ok[k] && ft < kFrontierCap) ? ft : 0];
-                if (ok[k] && ft >= kFrontierCap) {
-                    const int c = perm[a + ft];
-                    const int4 r = rec[c];
-                    e = make_int4(c, r.x, r.y, r.z);
-                }
-                v[k] = e.x;
-                w[k][0] = e.y;
-                w[k][1] = e.z;
-                w[k][2] = e.w;
-            }
-            // records of the neighbours: their label and their neighbours
-            int lw[kPer][3], x[kPer][3][3];
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-#pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    const int4 r = ok[k] ? rec[w[k][f]] : make_int4(0, 0, 0, 0);
-                    x[k][f][0] = r.x;
-                    x[k][f][1] = r.y;
-                    x[k][f][2] = r.z;
-                    lw[k][f] = r.w;
-                }
-            }
-            // an unlabelled neighbour ww is a child of v[k] when v[k] has the
-            // smallest label among ww's neighbours inside the frontier; the
-            // labels of ww's other neighbours are read for candidates only
-            bool cand[kPer][3];
-            int lx[kPer][3][3];
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-#pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    const int ww = w[k][f];
-                    cand[k][f] = ok[k] && ww != v[k] && !(f >= 1 && w[k][0] == ww) &&
-                                 !(f == 2 && w[k][1] == ww) && lw[k][f] == -1;
-#pragma unroll
-                    for (int g = 0; g < 3; ++g) {
-                        const int xg = x[k][f][g];
-                        lx[k][f][g] = (cand[k][f] && xg != v[k]) ? label[4 * xg + 3] : -1;
-                    }
-                }
-            }
-            bool child[kPer][3];
-            int kdeg[kPer][3];
-            int nk[kPer];
-            int total = 0;
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int lv = a + c0 + first + k;
-                nk[k] = 0;
-#pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    int owner = INT_MAX;
-#pragma unroll
-                    for (int g = 0; g < 3; ++g) {
-                        const int l = x[k][f][g] == v[k] ? lv : lx[k][f][g];
-                        if (l >= a && l < b && l < owner)
-                            owner = l;
-                    }
-                    child[k][f] = cand[k][f] && owner == lv;
-                    kdeg[k][f] = degree_of(w[k][f], x[k][f][0], x[k][f][1], x[k][f][2]);
-                    nk[k] += child[k][f];
-                }
-                total += nk[k];
-            }
             int sweep_total;
-            int pos = produced + block_exclusive_scan(total, scan_sh, &sweep_total);
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-#pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    if (child[k][f]) {
-                        int rank = 0;
-#pragma unroll
-                        for (int g = 0; g < 3; ++g) {
-                            const bool before = kdeg[k][g] < kdeg[k][f] ||
-                                                (kdeg[k][g] == kdeg[k][f] && w[k][g] < w[k][f]);
-                            rank += (g != f && child[k][g] && before);
-                        }
-                        const int p = pos + rank;
-                        const int lab = b + p;
-                        const int c = w[k][f];
-                        label[4 * c + 3] = lab;
-                        perm[lab] = c;
-                        if (p < kFrontierCap)
-                            frontier[cur ^ 1][p] = make_int4(c, x[k][f][0], x[k][f][1], x[k][f][2]);
-                    }
-                }
-                pos += nk[k];
-            }
+            if (per == 1)
+                sweep_total = cm_sweep<1>(rec, perm, lds, cur, a, b, c0, span, produced);
+            else if (per == 2)
+                sweep_total = cm_sweep<2>(rec, perm, lds, cur, a, b, c0, span, produced);
+            else
+                sweep_total = cm_sweep<3>(rec, perm, lds, cur, a, b, c0, span, produced);
             produced += sweep_total;
             // labels written by this sweep must be visible to the next one
             __threadfence_block();
@@ -293,48 +371,121 @@ __device__ __forceinline__ PassResult cm_pass(int4 *__restrict__ rec, int32_t ro
     return r;
 }
 
-// Cuthill-McKee order of each segment [seg[s], seg[s+1]) of the graph, one
-// workgroup per segment (no face may cross a segment boundary).  Within a
-// segment, components are taken in order of their lowest id; each one's root
-// is found by the George-Liu search from that id (label from the current
-// root, take the last level's cell of minimum (degree, id), relabel from it,
-// keep it while the eccentricity grows).  Output perm[label] = cell; permA
-// and permB are scratch of n entries.  A cell's record label is -1 until the
-// first pass reaches it, so the next component's root is the lowest cell
-// still at -1.  Every loop below ends on a block-uniform condition: each
-// component is labelled in full before the next starts, and the search
-// moves only while the eccentricity, bounded by the segment size, strictly
-// grows.
-__global__ __launch_bounds__(kCmThreads) void cm_segments_kernel(
-    int4 *__restrict__ rec, const int64_t *__restrict__ seg, int32_t *__restrict__ permA,
-    int32_t *__restrict__ permB, int32_t *__restrict__ perm, int32_t *__restrict__ passes)
+// Cuthill-McKee order of each segment [seg[s], seg[s+1]), one workgroup per
+// segment (no face may cross a segment boundary).  Within a segment,
+// components are taken in order of their lowest id; each one's root is found
+// by the George-Liu search from that id (label from the current root, take
+// the last level's cell of minimum (degree, id), relabel from it, keep it
+// while the eccentricity grows).  Output perm[label] = cell; permA and permB
+// are scratch of n entries.  A cell's record label is -1 until the first
+// pass reaches it, so the next component's root is the lowest cell still at
+// -1.
+//
+// The search's second pass over the first component usually only confirms
+// that the eccentricity does not grow, and level sets do not depend on the
+// order inside a level.  So that pass runs on a copy of the component's
+// graph renamed by the first pass's labels (rec2, built by
+// cm_translate_kernel), whose records lie far closer together in memory than
+// those of an arbitrary input order; only its eccentricity is used.  If it
+// exceeds the first pass's, the search continues exactly as above on the
+// original graph (where ties between children are broken by the original
+// ids).
+//
+// cm_first_kernel: the first pass of every segment (root: the segment's
+// lowest cell, into permA); state[s] = (cells labelled, eccentricity, pick).
+__global__ __launch_bounds__(kCmThreads) void cm_first_kernel(int4 *__restrict__ rec,
+                                                              const int64_t *__restrict__ seg,
+                                                              int32_t *__restrict__ permA,
+                                                              int4 *__restrict__ state)
 {
+    __shared__ PassLds lds;
+    const int s0 = (int)seg[blockIdx.x], s1 = (int)seg[blockIdx.x + 1];
+    if (s0 >= s1) {  // block-uniform; uploads reject empty segments
+        if (threadIdx.x == 0)
+            state[blockIdx.x] = make_int4(0, 0, s0, 0);
+        return;
+    }
+    const PassResult r = cm_pass(rec, s0, s0, permA, lds);
+    if (threadIdx.x == 0)
+        state[blockIdx.x] = make_int4(r.count, r.ecc, r.pick, 0);
+}
+
+// rec2[l] = (labels of the three neighbours of the cell labelled l, -1) for
+// every label l of a segment's first component (labels from the first pass,
+// which are also the positions in rec2); other positions are left alone.
+__global__ void cm_translate_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict__ seg,
+                                    const int4 *__restrict__ state, const int4 *__restrict__ rec,
+                                    const int32_t *__restrict__ permA, int4 *__restrict__ rec2)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n)
+        return;
+    int lo = 0, hi = n_seg - 1;  // segment of l: the last s with seg[s] <= l
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg[mid] <= l)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    if (l - (int)seg[lo] >= state[lo].x)
+        return;
+    const int4 r = rec[permA[l]];
+    rec2[l] = make_int4(rec[r.x].w, rec[r.y].w, rec[r.z].w, -1);
+}
+
+// The rest of the search for every segment, after cm_first_kernel and
+// cm_translate_kernel, as one loop with one labelling pass per iteration:
+// kProbe (the first component's pick, on the renamed copy), kRoot (the root
+// of the next component: its lowest unreached cell), kSearch (clear the
+// component's labels, relabel it from the pick of the best pass so far).
+// Every loop ends on a block-uniform condition: each component is labelled
+// in full before the next starts, and the search moves only while the
+// eccentricity, bounded by the segment size, strictly grows.
+__global__ __launch_bounds__(kCmThreads) void cm_finish_kernel(
+    int4 *__restrict__ rec, int4 *__restrict__ rec2, const int64_t *__restrict__ seg,
+    const int4 *__restrict__ state, int32_t *__restrict__ permA, int32_t *__restrict__ permB,
+    int32_t *__restrict__ perm, int32_t *__restrict__ passes)
+{
+    enum { kProbe, kRoot, kSearch };
     __shared__ PassLds lds;
     const int tid = threadIdx.x;
     const int s0 = (int)seg[blockIdx.x], s1 = (int)seg[blockIdx.x + 1];
     int32_t *rlabel = reinterpret_cast<int32_t *>(rec);
-    int npass = 0;
+    const int4 st = state[blockIdx.x];
+    PassResult rr;  // best pass of the current component
+    rr.count = st.x;
+    rr.ecc = st.y;
+    rr.pick = st.z;
+    int32_t *best = permA, *trial = permB;
+    int npass = s0 < s1 ? 1 : 0;
     int next = s0;
     int scan_from = s0;
-    while (next < s1) {
-        // lowest cell of the segment no pass has reached
-        int root = s1;
-        for (int c0 = scan_from; c0 < s1 && root == s1; c0 += kCmThreads) {
-            const int t = c0 + tid;
-            const unsigned long long key =
-                (t < s1 && rlabel[4 * t + 3] == -1) ? (unsigned long long)t : ~0ull;
-            const unsigned long long m = block_min_u64(key, lds.minv);
-            if (m != ~0ull)
-                root = (int)m;
-        }
-        if (root >= s1)  // block-uniform; cannot happen while next < s1
-            break;
-        scan_from = root;
-
-        int32_t *best = permA, *trial = permB;
-        PassResult rr = cm_pass(rec, root, next, best, lds);
-        ++npass;
-        for (;;) {
+    int mode = s0 < s1 ? kProbe : kRoot;
+    for (;;) {
+        int4 *graph = rec;
+        int root;
+        int32_t *out = trial;
+        if (mode == kProbe) {
+            graph = rec2;
+            root = rlabel[4 * rr.pick + 3];
+        } else if (mode == kRoot) {
+            if (next >= s1)
+                break;
+            root = s1;
+            for (int c0 = scan_from; c0 < s1 && root == s1; c0 += kCmThreads) {
+                const int t = c0 + tid;
+                const unsigned long long key =
+                    (t < s1 && rlabel[4 * t + 3] == -1) ? (unsigned long long)t : ~0ull;
+                const unsigned long long m = block_min_u64(key, lds.minv);
+                if (m != ~0ull)
+                    root = (int)m;
+            }
+            if (root >= s1)  // block-uniform; cannot happen while next < s1
+                break;
+            scan_from = root;
+            out = best;
+        } else {
             // Clear the component's labels before relabelling it: the first
             // component of a segment by a sweep over the whole segment (only
             // it and unreached cells live there), later ones cell by cell.
@@ -347,22 +498,33 @@ __global__ __launch_bounds__(kCmThreads) void cm_segments_kernel(
             }
             __threadfence_block();
             __syncthreads();
-            const PassResult rx = cm_pass(rec, rr.pick, next, trial, lds);
-            ++npass;
-            if (rx.ecc > rr.ecc) {
-                rr = rx;
+            root = rr.pick;
+        }
+        const PassResult r = cm_pass(graph, root, next, out, lds);
+        ++npass;
+        if (mode == kRoot) {
+            rr = r;
+            mode = kSearch;
+            continue;
+        }
+        if (r.ecc > rr.ecc) {
+            // a probe only reports the growth: the search then relabels
+            // exactly from the same pick
+            if (mode == kSearch) {
+                rr = r;
                 int32_t *t = best;
                 best = trial;
                 trial = t;
-            } else {
-                break;
             }
+            mode = kSearch;
+            continue;
         }
         for (int l = next + tid; l < next + rr.count; l += kCmThreads)
             perm[l] = best[l];
         __threadfence_block();
         __syncthreads();
         next += rr.count;
+        mode = kRoot;
     }
     if (tid == 0)
         passes[blockIdx.x] = npass;
@@ -409,13 +571,23 @@ hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *
     return hipGetLastError();
 }
 
-hipError_t launch_cm_segments(int4 *rec, int32_t n, int32_t n_seg, const int64_t *seg,
-                              int32_t *permA, int32_t *permB, int32_t *perm, int32_t *label,
-                              int32_t *passes, hipStream_t s)
+hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t n, int32_t n_seg,
+                              const int64_t *seg, int32_t *permA, int32_t *permB, int32_t *perm,
+                              int32_t *label, int32_t *passes, hipStream_t s)
 {
-    hipLaunchKernelGGL(cm_segments_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, seg, permA,
-                       permB, perm, passes);
+    hipLaunchKernelGGL(cm_first_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, seg, permA,
+                       state);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(cm_translate_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, n_seg, seg,
+                       state, rec, permA, rec2);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(cm_finish_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, rec2, seg,
+                       state, permA, permB, perm, passes);
+    e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(invert_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, label);

@@ -64,10 +64,13 @@ struct Layout {
         nrm = align_up(ld * 6 * 8);
         area = align_up(ld * 8);
         idx = align_up(ld * 4);
-        scratch = align_up(ld * 48);  // >= AoS normals (48 B), state (32 B), CM records + orders (24 B)
-        // segment offsets (int64), per-segment dt (double), per-segment pass counts (int32)
+        // >= AoS normals (48 B), state (32 B), CM records, two orders and
+        // renamed records (40 B)
+        scratch = align_up(ld * 48);
+        // segment offsets (int64), per-segment dt (double), per-segment pass
+        // counts (int32), per-segment first-pass results (int4)
         seg = align_up((size_t)(kMaxSegments + 1) * 8) + align_up((size_t)kMaxSegments * 8) +
-              align_up((size_t)kMaxSegments * 4);
+              align_up((size_t)kMaxSegments * 4) + align_up((size_t)kMaxSegments * 16);
         corr = align_up(fvk::kCorrFragShorts * 2) + align_up(fvk::kCorrBias * 4) +
                align_up(fvk::kCorrAdjFragShorts * 2) +
                align_up((size_t)fvk::kCorrAdjMaxGrid * fvk::kCorrParams * 4);
@@ -103,6 +106,7 @@ struct fv_ctx {
     int64_t *seg_dev = nullptr;   // segment offsets (n_seg + 1)
     double *dt_dev = nullptr;     // per-segment dt of `coef`
     int32_t *passes_dev = nullptr;
+    int4 *cm_state = nullptr;     // per-segment first-pass results of the renumbering
 
     int32_t n_seg = 1;
     std::vector<int64_t> seg_host;  // segment offsets; a segment is an independent mesh
@@ -220,7 +224,8 @@ fv_status regather_geometry(fv_ctx *c)
 
 // Cuthill-McKee labelling of every segment of the uploaded graph into
 // c->perm / c->label, one workgroup per segment, all on the device.
-// Scratch use (bytes per cell): records 16, two candidate orders 4 + 4.
+// Scratch use (bytes per cell): records 16, two candidate orders 4 + 4,
+// renamed records 16 (ld is a multiple of 64, so every part stays aligned).
 fv_status cm_order(fv_ctx *c)
 {
     const int32_t n = c->n;
@@ -228,9 +233,10 @@ fv_status cm_order(fv_ctx *c)
     int4 *rec = reinterpret_cast<int4 *>(c->scratch);
     int32_t *permA = reinterpret_cast<int32_t *>(rec + ld);
     int32_t *permB = permA + ld;
+    int4 *rec2 = reinterpret_cast<int4 *>(permB + ld);
     HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
-    HIP_TRY(fvk::launch_cm_segments(rec, n, c->n_seg, c->seg_dev, permA, permB, c->perm,
-                                    c->label, c->passes_dev, c->stream));
+    HIP_TRY(fvk::launch_cm_segments(rec, rec2, c->cm_state, n, c->n_seg, c->seg_dev, permA,
+                                    permB, c->perm, c->label, c->passes_dev, c->stream));
     return FV_OK;
 }
 
@@ -394,6 +400,8 @@ fv_status fv_create(int64_t n_cells, double gamma, void *d_arena, size_t arena_b
     p += align_up((size_t)kMaxSegments * 8);
     c->passes_dev = reinterpret_cast<int32_t *>(p);
     p += align_up((size_t)kMaxSegments * 4);
+    c->cm_state = reinterpret_cast<int4 *>(p);
+    p += align_up((size_t)kMaxSegments * 16);
     c->corr_frags = reinterpret_cast<short *>(p);
     p += align_up(fvk::kCorrFragShorts * 2);
     c->corr_bias = reinterpret_cast<float *>(p);
