@@ -38,18 +38,19 @@ if ROOT not in sys.path:
 # neighbour states counted as the cache reuse the renumbering provides.
 # General layout: read U 32 + neighbour ids 12 + normals 48 + 1/area 8,
 # write U 32 = 132; with 16-bit neighbour offsets and the derived third
-# normal (the layout of this workload after renumbering) 112.
+# normal 112; with, in addition, the two stored normals in 32-bit fixed point
+# (the layout of this workload after renumbering) 96.
 HBM_PEAK_GBS = 8000.0
 STEP_SOURCE = os.path.join(ROOT, "paper_1408_5715_amd", "csrc", "fv_step.hip")
 
-# HBM traffic of one step launch on this workload (renumbered order, 112-byte
+# HBM traffic of one step launch on this workload (renumbered order, 96-byte
 # layout), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs, each scaled
 # by what the counter reads for a plain 256 MiB copy in the same run (x2.000
 # and x1.000).  Valid only for the step kernel source with this SHA-256.
 MEASURED_TRAFFIC = {
-    "source_sha": "6c72436b4da61f8a93c3d89355655ecf1f9072f5330eb758d42101231a9436de",
+    "source_sha": "02f9e3bbb22d696456438d6eaa9d030eb978559f05820e45870a06d81af9a197",
     "cells": 2097152,
-    "bytes_per_launch": 235953889,  # fetch 168,846,284 + write 67,107,605
+    "bytes_per_launch": 202402695,  # fetch 135,295,826 + write 67,106,869
 }
 
 

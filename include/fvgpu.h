@@ -259,8 +259,11 @@ fv_status fv_download_state_device(fv_ctx *ctx, double *d_U);
  * current layout: the state read and written (32 + 32), 1/V_T (8), the
  * neighbour indices (12 as 32-bit ids, or 8 as 16-bit offsets when the
  * current order keeps every neighbour within 32767 cells) and the face
- * normals (48, or 32 when every cell's normals satisfy n_2 = -(n_0 + n_1)
- * exactly and the third is derived).  Neighbour states are counted as cache
+ * normals (48; 32 when every cell's normals satisfy n_2 = -(n_0 + n_1)
+ * exactly and the third is derived; 16 when, in addition, every component of
+ * the first two is an integer multiple of 2^-32 smaller than 1/2 in size, as
+ * on meshes snapped to 2^-32, and they are stored as 32-bit fixed-point
+ * values that decode to the same doubles).  Neighbour states are counted as cache
  * hits (the reuse the renumbering of section 4 provides).  Returns 0 on a
  * null context or before the mesh is uploaded.
  */

@@ -8,6 +8,7 @@
 //   nrm     double [6][ld]    nx_0, ny_0, nx_1, ny_1, nx_2, ny_2
 //   inv_area double [ld]      1 / V_T
 //   nb16    short4 [ld]       neighbour offsets j - i, when they fit in 16 bits
+//   nfx     int4   [ld]       first two normals in fixed point, when exact
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,11 +22,18 @@ namespace fvk {
 // with coef[i] = dt / V_i.
 // narrow: read neighbours from nb16 (16-bit offsets) instead of nb.
 // closed: take the third normal as -(n_0 + n_1) instead of reading it.
+// fixed (with closed): read the first two normals from nfx (fixed point).
 // block: 128, 256 or 512 threads; grid: 0 = one workgroup per tile of
 // `block` cells, else that many persistent workgroups.
 hipError_t launch_step(int32_t n, int32_t ld, const double4 *U, double4 *Un, const int32_t *nb,
-                       const short4 *nb16, const double *nrm, const double *coef, double gamma,
-                       bool narrow, bool closed, int block, int grid, hipStream_t s);
+                       const short4 *nb16, const double *nrm, const int4 *nfx,
+                       const double *coef, double gamma, bool narrow, bool closed, bool fixed,
+                       int block, int grid, hipStream_t s);
+
+// nfx[i] = (k_0x, k_0y, k_1x, k_1y), the first two normals of cell i as
+// n = k 2^-32 (INT32_MIN for -0.0); every component must convert exactly.
+hipError_t launch_fixed_normals(int32_t n, int32_t ld, const double *nrm, int4 *nfx,
+                                hipStream_t s);
 
 // coef[i] = dt[s] * inv_area[i], s the segment of cell i.
 hipError_t launch_coef(int32_t n, int32_t n_seg, const int64_t *seg, const double *dt,

@@ -54,13 +54,14 @@ int64_t leading_dim(int64_t n)
 
 // Byte sizes of the arena regions for n cells (leading dimension ld).
 struct Layout {
-    size_t U, nb, nb16, nrm, area, idx, scratch, seg, corr, small, total;
+    size_t U, nb, nb16, nfx, nrm, area, idx, scratch, seg, corr, small, total;
     explicit Layout(int64_t n)
     {
         const size_t ld = (size_t)leading_dim(n);
         U = align_up(ld * 32);
         nb = align_up(ld * 3 * 4);
         nb16 = align_up(ld * 8);
+        nfx = align_up(ld * 16);
         nrm = align_up(ld * 6 * 8);
         area = align_up(ld * 8);
         idx = align_up(ld * 4);
@@ -75,7 +76,8 @@ struct Layout {
                align_up(fvk::kCorrAdjFragShorts * 2) +
                align_up((size_t)fvk::kCorrAdjMaxGrid * fvk::kCorrParams * 4);
         small = kAlign;
-        total = 2 * U + 2 * nb + nb16 + 2 * nrm + 3 * area + 2 * idx + scratch + seg + corr + small;
+        total = 2 * U + 2 * nb + nb16 + nfx + 2 * nrm + 3 * area + 2 * idx + scratch + seg + corr +
+                small;
     }
 };
 
@@ -96,6 +98,7 @@ struct fv_ctx {
     double *area_o = nullptr;
     int32_t *nb_w = nullptr;  // working (renumbered) order
     short4 *nb16_w = nullptr; // ... as 16-bit offsets, valid when `narrow`
+    int4 *nfx_w = nullptr;    // first two normals of the working order in fixed point, when `fixed`
     double *nrm_w = nullptr;
     double *inv_area_w = nullptr;
     double *coef = nullptr;    // dt / V_T per working cell, for coef_dt
@@ -128,6 +131,7 @@ struct fv_ctx {
     bool mesh_ready = false;
     bool state_ready = false;
     bool closed = false;  // every cell: n_2 == -(n_0 + n_1) exactly
+    bool fixed = false;   // every n_0, n_1 component is k 2^-32, |k| < 2^31 (and `closed`)
     bool narrow = false;  // every neighbour offset of the working order fits in 16 bits
 };
 
@@ -193,6 +197,21 @@ fv_status validate_state(int64_t n, const double *U, double gamma)
     return FV_OK;
 }
 
+// Every component of every cell's first two normals is an integer multiple
+// k of 2^-32 with |k| < 2^31, so it converts to a 32-bit fixed-point value
+// and back exactly (-0.0 is kept apart).
+bool normals_fixed(int64_t n, const double *nrm)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        for (int c = 0; c < 4; ++c) {
+            const double k = nrm[6 * i + c] * 0x1p32;  // exact: a power of two
+            if (!(k == std::trunc(k) && std::fabs(k) < 0x1p31))
+                return false;
+        }
+    }
+    return true;
+}
+
 // Every cell's third normal equals -(n_0 + n_1) in binary64 (true when the
 // normals are exact coordinate differences, as on snapped meshes).
 bool normals_closed(int64_t n, const double *nrm)
@@ -218,6 +237,9 @@ fv_status regather_geometry(fv_ctx *c)
     HIP_TRY(hipMemcpyAsync(&too_far, dflag, sizeof(too_far), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->narrow = too_far == 0;
+    if (c->fixed) {
+        HIP_TRY(fvk::launch_fixed_normals(c->n, c->ld, c->nrm_w, c->nfx_w, c->stream));
+    }
     c->coef_dt.clear();
     return FV_OK;
 }
@@ -279,8 +301,8 @@ hipError_t launch_one(fv_ctx *c, int from, hipStream_t st)
                                         c->nb16_w, c->nrm_w, c->coef, c->inv_area_w, c->corr_frags,
                                         c->corr_bias, c->gamma, c->narrow, c->closed, c->grid, st);
     return fvk::launch_step(c->n, c->ld, c->U[from], c->U[from ^ 1], c->nb_w, c->nb16_w,
-                            c->nrm_w, c->coef, c->gamma, c->narrow, c->closed, c->block, c->grid,
-                            st);
+                            c->nrm_w, c->nfx_w, c->coef, c->gamma, c->narrow, c->closed, c->fixed,
+                            c->block, c->grid, st);
 }
 
 // n_steps launches of the step, ping-ponging the state buffers; through a
@@ -297,7 +319,7 @@ fv_status run_steps(fv_ctx *c, int32_t n_steps)
         return FV_OK;
     }
     const long long key[6] = {n_steps, c->cur, c->block, c->grid,
-                              c->narrow + 2 * c->closed + 4 * c->corr_on, 0};
+                              c->narrow + 2 * c->closed + 4 * c->corr_on + 8 * c->fixed, 0};
     bool hit = c->graph_exec != nullptr;
     for (int k = 0; hit && k < 6; ++k)
         hit = key[k] == c->graph_key[k];
@@ -378,6 +400,8 @@ fv_status fv_create(int64_t n_cells, double gamma, void *d_arena, size_t arena_b
     p += lay.nb;
     c->nb16_w = reinterpret_cast<short4 *>(p);
     p += lay.nb16;
+    c->nfx_w = reinterpret_cast<int4 *>(p);
+    p += lay.nfx;
     c->nrm_o = reinterpret_cast<double *>(p);
     p += lay.nrm;
     c->nrm_w = reinterpret_cast<double *>(p);
@@ -453,6 +477,7 @@ fv_status upload(fv_ctx *c, int32_t n_seg, const int64_t *seg, const int32_t *nb
     c->state_ready = false;
     drop_graph(c);
     c->closed = normals_closed(c->n, nrm);
+    c->fixed = c->closed && normals_fixed(c->n, nrm);
     c->n_seg = n_seg;
     c->seg_host.assign(seg, seg + n_seg + 1);
     HIP_TRY(hipMemcpyAsync(c->seg_dev, c->seg_host.data(), (n_seg + 1) * sizeof(int64_t),
@@ -743,7 +768,7 @@ int64_t fv_bytes_per_update(const fv_ctx *c)
 {
     if (!c || !c->mesh_ready)
         return 0;
-    return 32 + 32 + 8 + (c->narrow ? 8 : 12) + (c->closed ? 32 : 48);
+    return 32 + 32 + 8 + (c->narrow ? 8 : 12) + (c->fixed ? 16 : (c->closed ? 32 : 48));
 }
 
 fv_status fv_check_state(fv_ctx *c)

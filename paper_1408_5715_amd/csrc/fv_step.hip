@@ -29,7 +29,14 @@
 //   - kClosed: the third normal read as -(n_0 + n_1) instead of from memory;
 //     used when every cell's stored normals satisfy n_2 == -(n_0 + n_1)
 //     exactly, so the value is bit-identical to the stored one.
-// Bytes per cell update: 132 (general), 112 with both.  The cell's
+//   - kFixed (with kClosed): the two stored normals as 32-bit integers k with
+//     n = k 2^-32, four ints (16 bytes) instead of four doubles; used when
+//     every such component is an integer multiple of 2^-32 below 2^31 in
+//     size (as on meshes whose vertices are snapped to 2^-32, with faces
+//     shorter than 1/2), so the decoded double is the stored one; -0.0 is
+//     kept as the otherwise unused INT32_MIN.
+// Bytes per cell update: 132 (general), 112 with the first two, 96 with all
+// three.  The cell's
 // dt / V_T comes from a per-cell array (formed as dt * (1 / V_T), the same
 // single rounding whatever the batch), so meshes of a batch can step with
 // their own dt in one launch.
@@ -95,13 +102,21 @@ __device__ __forceinline__ Prim primitives(const double4 &U, double gamma)
     return q;
 }
 
+// A normal component from its fixed-point form k (n = k 2^-32; INT32_MIN
+// stands for -0.0).
+__device__ __forceinline__ double from_fixed(int k)
+{
+    return k == INT32_MIN ? -0.0 : (double)k * 0x1p-32;
+}
+
 // Update of one cell i (the body of the step).
-template <bool kNarrow, bool kClosed>
+template <bool kNarrow, bool kClosed, bool kFixed>
 __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__restrict__ U,
                                             double4 *__restrict__ Un,
                                             const int32_t *__restrict__ nb,
                                             const short4 *__restrict__ nb16,
                                             const double *__restrict__ nrm,
+                                            const int4 *__restrict__ nfx,
                                             const double *__restrict__ coef, double gamma)
 {
     int js[3];
@@ -116,10 +131,18 @@ __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__
         js[2] = nb[2 * ld + i];
     }
     double nxs[3], nys[3];
-    nxs[0] = nrm[i];
-    nys[0] = nrm[ld + i];
-    nxs[1] = nrm[2 * ld + i];
-    nys[1] = nrm[3 * ld + i];
+    if constexpr (kFixed) {
+        const int4 q = nfx[i];
+        nxs[0] = from_fixed(q.x);
+        nys[0] = from_fixed(q.y);
+        nxs[1] = from_fixed(q.z);
+        nys[1] = from_fixed(q.w);
+    } else {
+        nxs[0] = nrm[i];
+        nys[0] = nrm[ld + i];
+        nxs[1] = nrm[2 * ld + i];
+        nys[1] = nrm[3 * ld + i];
+    }
     if constexpr (kClosed) {
         nxs[2] = -(nxs[0] + nxs[1]);
         nys[2] = -(nys[0] + nys[1]);
@@ -167,11 +190,12 @@ __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__
 // remapped so that each XCD takes one contiguous range of tiles; with a
 // persistent grid of fewer workgroups, the tiles are split into one
 // contiguous range per XCD and the workgroups of each XCD stride through it.
-template <int kBlock, bool kNarrow, bool kClosed>
+template <int kBlock, bool kNarrow, bool kClosed, bool kFixed>
 __global__ __launch_bounds__(kBlock) void fv_step_kernel(
     int32_t n, int32_t ld, const double4 *__restrict__ U, double4 *__restrict__ Un,
     const int32_t *__restrict__ nb, const short4 *__restrict__ nb16,
-    const double *__restrict__ nrm, const double *__restrict__ coef, double gamma)
+    const double *__restrict__ nrm, const int4 *__restrict__ nfx,
+    const double *__restrict__ coef, double gamma)
 {
     const int tiles = (n + kBlock - 1) / kBlock;
     const int G = gridDim.x, b = blockIdx.x;
@@ -179,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void fv_step_kernel(
         const int t = xcd_contiguous_block(b, G);
         const int i = t * kBlock + threadIdx.x;
         if (t < tiles && i < n)
-            update_cell<kNarrow, kClosed>(i, ld, U, Un, nb, nb16, nrm, coef, gamma);
+            update_cell<kNarrow, kClosed, kFixed>(i, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma);
         return;
     }
     const int X = G < kXcds ? G : kXcds;  // XCDs that hold workgroups
@@ -189,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void fv_step_kernel(
     for (int t = t0 + k; t < t1; t += Px) {
         const int i = t * kBlock + threadIdx.x;
         if (i < n)
-            update_cell<kNarrow, kClosed>(i, ld, U, Un, nb, nb16, nrm, coef, gamma);
+            update_cell<kNarrow, kClosed, kFixed>(i, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma);
     }
 }
 
@@ -213,26 +237,36 @@ __global__ void coef_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict_
     coef[i] = dt[lo] * inv_area[i];
 }
 
+template <int kBlock, bool kNarrow, bool kClosed, bool kFixed>
+void launch_variant(int G, int32_t n, int32_t ld, const double4 *U, double4 *Un,
+                    const int32_t *nb, const short4 *nb16, const double *nrm, const int4 *nfx,
+                    const double *coef, double gamma, hipStream_t s)
+{
+    hipLaunchKernelGGL((fv_step_kernel<kBlock, kNarrow, kClosed, kFixed>), dim3(G), dim3(kBlock),
+                       0, s, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma);
+}
+
 template <int kBlock>
 hipError_t launch_step_block(int32_t n, int32_t ld, const double4 *U, double4 *Un,
                              const int32_t *nb, const short4 *nb16, const double *nrm,
-                             const double *coef, double gamma, bool narrow, bool closed,
-                             int grid, hipStream_t s)
+                             const int4 *nfx, const double *coef, double gamma, bool narrow,
+                             bool closed, bool fixed, int grid, hipStream_t s)
 {
     const int tiles = (n + kBlock - 1) / kBlock;
     const int G = (grid <= 0 || grid > tiles) ? tiles : grid;
-    if (narrow && closed)
-        hipLaunchKernelGGL((fv_step_kernel<kBlock, true, true>), dim3(G), dim3(kBlock), 0, s, n,
-                           ld, U, Un, nb, nb16, nrm, coef, gamma);
+    fixed = fixed && closed;
+    if (narrow && fixed)
+        launch_variant<kBlock, true, true, true>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, s);
+    else if (fixed)
+        launch_variant<kBlock, false, true, true>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, s);
+    else if (narrow && closed)
+        launch_variant<kBlock, true, true, false>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, s);
     else if (narrow)
-        hipLaunchKernelGGL((fv_step_kernel<kBlock, true, false>), dim3(G), dim3(kBlock), 0, s,
-                           n, ld, U, Un, nb, nb16, nrm, coef, gamma);
+        launch_variant<kBlock, true, false, false>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, s);
     else if (closed)
-        hipLaunchKernelGGL((fv_step_kernel<kBlock, false, true>), dim3(G), dim3(kBlock), 0, s,
-                           n, ld, U, Un, nb, nb16, nrm, coef, gamma);
+        launch_variant<kBlock, false, true, false>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, s);
     else
-        hipLaunchKernelGGL((fv_step_kernel<kBlock, false, false>), dim3(G), dim3(kBlock), 0, s,
-                           n, ld, U, Un, nb, nb16, nrm, coef, gamma);
+        launch_variant<kBlock, false, false, false>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, s);
     return hipGetLastError();
 }
 
@@ -252,25 +286,53 @@ __global__ void narrow_offsets_kernel(int32_t n, int32_t ld, const int32_t *__re
         *too_far = 1;
 }
 
+// nfx[i] = the fixed-point form of the first two normals of working cell i
+// (the mesh was checked on the host: every component converts exactly).
+__global__ void fixed_normals_kernel(int32_t n, int32_t ld, const double *__restrict__ nrm,
+                                     int4 *__restrict__ nfx)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n)
+        return;
+    int k[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double x = nrm[c * ld + i];
+        k[c] = (x == 0.0 && signbit(x)) ? INT32_MIN : (int)(x * 0x1p32);
+    }
+    nfx[i] = make_int4(k[0], k[1], k[2], k[3]);
+}
+
 }  // namespace
 
 hipError_t launch_step(int32_t n, int32_t ld, const double4 *U, double4 *Un, const int32_t *nb,
-                       const short4 *nb16, const double *nrm, const double *coef, double gamma,
-                       bool narrow, bool closed, int block, int grid, hipStream_t s)
+                       const short4 *nb16, const double *nrm, const int4 *nfx,
+                       const double *coef, double gamma, bool narrow, bool closed, bool fixed,
+                       int block, int grid, hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
     switch (block) {
     case 128:
-        return launch_step_block<128>(n, ld, U, Un, nb, nb16, nrm, coef, gamma, narrow, closed,
-                                      grid, s);
+        return launch_step_block<128>(n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, narrow,
+                                      closed, fixed, grid, s);
     case 512:
-        return launch_step_block<512>(n, ld, U, Un, nb, nb16, nrm, coef, gamma, narrow, closed,
-                                      grid, s);
+        return launch_step_block<512>(n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, narrow,
+                                      closed, fixed, grid, s);
     default:
-        return launch_step_block<256>(n, ld, U, Un, nb, nb16, nrm, coef, gamma, narrow, closed,
-                                      grid, s);
+        return launch_step_block<256>(n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, narrow,
+                                      closed, fixed, grid, s);
     }
+}
+
+hipError_t launch_fixed_normals(int32_t n, int32_t ld, const double *nrm, int4 *nfx,
+                                hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(fixed_normals_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ld, nrm,
+                       nfx);
+    return hipGetLastError();
 }
 
 hipError_t launch_coef(int32_t n, int32_t n_seg, const int64_t *seg, const double *dt,

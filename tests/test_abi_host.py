@@ -42,7 +42,7 @@ def test_arena_bytes():
     assert 240 * 8192 <= b <= 300 * 8192 + fixed
     assert fv.fv_arena_bytes(8193) >= b
     big = fv.fv_arena_bytes(1 << 21)
-    assert 250 * (1 << 21) <= big <= 280 * (1 << 21) + fixed
+    assert 250 * (1 << 21) <= big <= 300 * (1 << 21) + fixed
 
 
 def make_ctx(n):

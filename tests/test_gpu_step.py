@@ -369,6 +369,33 @@ def test_gpu_cm_search_that_moves(torch, length, seed):
     assert passes == gl + 1
 
 
+def test_fixed_point_normals_only_when_exact(torch):
+    """A closed mesh whose faces are longer than 1/2 keeps its normals in
+    float64 (112 bytes per update) and still matches the oracle; the
+    fixed-point form of a fine snapped mesh decodes to the same bits as the
+    float64 one (the corrected step with zero parameters reads the float64
+    normals and equals the plain step bitwise, tested with the correction)."""
+    m, U0, dt = vortex_case(8)  # h = 1.25
+    assert np.abs(m.nrm).max() >= 0.5
+    ref = oracle.step(m.nbr, m.nrm, m.area, U0, dt, 50)
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        s.upload_state(U0)
+        assert s.bytes_per_update() == 32 + 32 + 8 + 8 + 32
+        s.step(50, dt)
+        got = s.download()
+    finally:
+        s.close()
+    assert np.all(rel_err(got, ref) <= TOL), rel_err(got, ref)
+    fine, _, _ = vortex_case(64)
+    assert np.any((fine.nrm == 0.0) & np.signbit(fine.nrm))  # -0.0 components occur
+    s = fv.Solver(fine.nbr, fine.nrm, fine.area)
+    try:
+        assert s.bytes_per_update() == 32 + 32 + 8 + 8 + 16
+    finally:
+        s.close()
+
+
 def open_normals(m, fraction=0.05, seed=9):
     """Scale the normals of some face pairs by (1 + 2^-20) on both sides:
     antisymmetry stays exact, closure n_2 = -(n_0 + n_1) no longer holds."""
@@ -386,9 +413,9 @@ def open_normals(m, fraction=0.05, seed=9):
 @pytest.mark.parametrize("closed", [True, False])
 @pytest.mark.parametrize("order", [fv.FV_ORDER_IDENTITY, fv.FV_ORDER_CM])
 def test_layout_variants(torch, closed, order):
-    """All four geometry layouts of the step (16-bit offsets or 32-bit ids,
-    derived or stored third normal) agree with the oracle, and runs that
-    differ only in the cell order agree bitwise."""
+    """The geometry layouts of the step (16-bit offsets or 32-bit ids;
+    normals in fixed point with the third derived, or the third derived, or
+    all stored) agree with the oracle."""
     N = 160  # 51,200 cells: a random order has offsets beyond 16 bits, CM's do not
     m, U0, dt = vortex_case(N)
     nrm = m.nrm if closed else open_normals(m)
@@ -398,7 +425,8 @@ def test_layout_variants(torch, closed, order):
     try:
         s.upload_state(U0)
         s.renumber(order)
-        want = 32 + 32 + 8 + (8 if order == fv.FV_ORDER_CM else 12) + (32 if closed else 48)
+        # the snapped mesh's normals are multiples of 2^-32 well below 1/2
+        want = 32 + 32 + 8 + (8 if order == fv.FV_ORDER_CM else 12) + (16 if closed else 48)
         assert s.bytes_per_update() == want
         s.step(100, dt)
         got = s.download()
