@@ -237,7 +237,11 @@ fv_status fv_set_launch(fv_ctx *ctx, int32_t block, int32_t grid, int32_t use_gr
 /*
  * Number of labelling passes (breadth-first sweeps of section 4's
  * renumbering, including the pseudo-peripheral search) each mesh took in the
- * last fv_renumber with FV_ORDER_CM.
+ * last fv_renumber with FV_ORDER_CM.  The search's second sweep over a mesh's
+ * first component runs on a copy of the graph renamed by the first sweep's
+ * labels (same eccentricity, better memory locality); when that eccentricity
+ * is larger, the search repeats the sweep on the original graph, so such a
+ * mesh counts one pass more than the sequential search takes.
  *   passes  host int32 [n_meshes].  Synchronises the stream.
  */
 fv_status fv_renumber_passes(fv_ctx *ctx, int32_t *passes);
