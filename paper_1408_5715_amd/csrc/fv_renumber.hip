@@ -29,10 +29,13 @@
 // neighbour lists in LDS (fetched when they were discovered), with a mask of
 // the neighbours already known to be labelled then (the owner, and any whose
 // label the discovery read); their records are not fetched again, since a
-// labelled cell is never a child.  One CU runs the whole labelling, and its
-// cost is set by the latency of scattered loads, so loads are issued only by
-// the lanes that need them (the records of the neighbours not known to be
-// labelled, and the labels of the other neighbours of unlabelled cells).
+// labelled cell is never a child.  One CU runs the whole labelling; its cost
+// is shared between the CU's path for scattered loads, its VALU and the
+// synchronisation of each level, so loads are issued only by the lanes that
+// need them (the records of the neighbours not known to be labelled, and the
+// labels of the other neighbours of unlabelled cells), a sweep issues all its
+// record loads before waiting for the first, and the sweep's code exists for
+// 1, 2 and 3 frontier cells per thread so that no thread runs empty slots.
 
 #include <climits>
 
