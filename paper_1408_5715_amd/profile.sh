@@ -11,6 +11,11 @@
 # kernels (paper_1408_5715_amd/profile_learned.py: 20 corrected steps on the
 # 1024 x 1024 mesh, 4 corrected adjoint steps on the 32-flow training batch),
 # with MFMA counters in place of the byte counters.  Output gpurun_out/lprof_*.
+#
+# `profile.sh renumber`: two counter passes (wave and instruction counters;
+# texture-addresser, L1-to-L2 and clock counters) over one bench.py job of
+# the 2,097,152-cell workload, for the renumbering kernels and the step.
+# Output gpurun_out/rprof_*.  Summarise with profile_summary.py renumber.
 set -euo pipefail
 ROOT="$(cd "$(dirname "$0")/.." && pwd)"
 OUT="$ROOT/gpurun_out"
@@ -18,6 +23,20 @@ mkdir -p "$OUT"
 export TMPDIR=/tmp
 export PYTHONPATH="$ROOT${PYTHONPATH:+:$PYTHONPATH}"
 cd /tmp
+if [ "${1:-}" = "renumber" ]; then
+    # one job of bench.py (renumbering + 20 steps) under two counter passes
+    JOB=(python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random)
+    echo "[profile] renumber: SQ counters" >&2
+    timeout -s KILL 120 rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY \
+        SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_INSTS_VALU SQ_INSTS_VMEM_RD -f csv \
+        -d "$OUT/rprof_sq" -o sq -- "${JOB[@]}" > "$OUT/rprof_sq.log" 2>&1
+    echo "[profile] renumber: memory-path counters" >&2
+    timeout -s KILL 120 rocprofv3 --pmc TA_TA_BUSY TA_ADDR_STALLED_BY_TC_CYCLES TCP_TCC_READ_REQ \
+        TCP_TCC_READ_REQ_LATENCY GRBM_GUI_ACTIVE SQ_INSTS_LDS -f csv \
+        -d "$OUT/rprof_mem" -o mem -- "${JOB[@]}" > "$OUT/rprof_mem.log" 2>&1
+    echo "[profile] done" >&2
+    exit 0
+fi
 if [ "${1:-}" = "learned" ]; then
     echo "[profile] learned: kernel trace" >&2
     timeout -k 10 300 rocprofv3 --kernel-trace --stats -f csv -d "$OUT/lprof_trace" -o trace -- \

@@ -146,7 +146,56 @@ def main_learned() -> int:
     return 0
 
 
+def per_dispatch(path):
+    """{kernel: {counter: mean value per dispatch}} of a counter run."""
+    agg = {}
+    for r in csv.DictReader(open(path)):
+        agg.setdefault(short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+            float(r["Counter_Value"]))
+    return {k: {c: st.mean(v) for c, v in d.items()} for k, d in agg.items()}
+
+
+def main_renumber() -> int:
+    """Counters of the renumbering kernels and the step (profile.sh renumber).
+    SQ cycle counters are in units of 4 cycles; TA and TCP counters sum over
+    the CUs (one CU for a renumbering kernel, all 256 for the step)."""
+    sq = per_dispatch(os.path.join(OUT, "rprof_sq", "sq_counter_collection.csv"))
+    mem = per_dispatch(os.path.join(OUT, "rprof_mem", "mem_counter_collection.csv"))
+    step = "void fv_step_kernel<256, true, true, true>"
+    rows = [("cm_first_kernel", 1, 1366), ("cm_translate_kernel", 256, 0),
+            ("cm_finish_kernel", 1, 1366), (step, 256, 0)]
+    lines = ["| kernel | cycles | waves | VALU / wave | VMEM reads / wave | VALU busy / SIMD "
+             "| waves waiting: any / on data | TA busy / stalled by L1 | L1->L2 reads "
+             "| L2 read latency (cycles) |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    for k, cus, levels in rows:
+        if k not in sq or k not in mem:
+            continue
+        q, m = sq[k], mem[k]
+        cycles = m["GRBM_GUI_ACTIVE"] / XCDS
+        waves = q["SQ_WAVES"]
+        valu_busy = q["SQ_ACTIVE_INST_VALU"] * 4 / (cus * 4 * cycles)
+        lines.append(
+            f"| {k} | {cycles:.3g} | {waves:.0f} | {q['SQ_INSTS_VALU'] / waves:.0f} | "
+            f"{q['SQ_INSTS_VMEM_RD'] / waves:.1f} | {valu_busy:.2f} | "
+            f"{q['SQ_WAIT_ANY'] / q['SQ_WAVE_CYCLES']:.2f} / "
+            f"{q['SQ_WAIT_INST_ANY'] / q['SQ_WAVE_CYCLES']:.2f} | "
+            f"{m['TA_TA_BUSY'] / (cus * cycles):.2f} / "
+            f"{m['TA_ADDR_STALLED_BY_TC_CYCLES'] / (cus * cycles):.2f} | "
+            f"{m['TCP_TCC_READ_REQ']:.3g} | "
+            f"{m['TCP_TCC_READ_REQ_LATENCY'] / max(m['TCP_TCC_READ_REQ'], 1):.0f} |")
+        if levels:
+            lines.append(f"| (per level) | {cycles / levels:.0f} | | "
+                         f"{q['SQ_INSTS_VALU'] / waves / levels:.0f} | "
+                         f"{q['SQ_INSTS_VMEM_RD'] / waves / levels:.1f} | | | | "
+                         f"{m['TCP_TCC_READ_REQ'] / levels:.0f} | |")
+    print("\n".join(lines))
+    return 0
+
+
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "learned":
         sys.exit(main_learned())
+    if len(sys.argv) > 1 and sys.argv[1] == "renumber":
+        sys.exit(main_renumber())
     sys.exit(main())
