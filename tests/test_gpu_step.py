@@ -10,7 +10,8 @@ import pytest
 
 import oracle
 import paper_1408_5715_amd as fv
-from gpu_helpers import TOL, bumps_case, conserved_totals, log, rel_err, vortex_case
+from gpu_helpers import (TOL, bumps_case, conserved_totals, george_liu_passes, ladder_graph, log,
+                         rel_err, vortex_case)
 
 pytestmark = pytest.mark.gpu
 
@@ -285,63 +286,6 @@ def test_gpu_cm_wide_levels(torch):
     finally:
         s.close()
     assert np.array_equal(perm, oracle.cm_order(nbr))
-
-
-def ladder_graph(length: int):
-    """A ladder of `length` rungs (cell 2 i + s on rail s), every cell of
-    degree 3 through a doubled rung at both ends: from a cell in the middle
-    the pseudo-peripheral search moves to an end (the eccentricity grows), so
-    the search takes the path beyond its first confirmation pass."""
-    edges = []
-    for i in range(length):
-        edges.append((2 * i, 2 * i + 1))
-        if i + 1 < length:
-            edges += [(2 * i, 2 * i + 2), (2 * i + 1, 2 * i + 3)]
-    edges += [(0, 1), (2 * length - 2, 2 * length - 1)]
-    n = 2 * length
-    adj = [[] for _ in range(n)]
-    for u, v in edges:
-        adj[u].append(v)
-        adj[v].append(u)
-    assert all(len(a) == 3 for a in adj)
-    nbr = np.array(adj, dtype=np.int32)
-    nrm = np.empty((n, 3, 2))
-    for u in range(n):
-        for f, v in enumerate(adj[u]):
-            sgn = 1.0 if u < v else -1.0
-            nrm[u, f] = (sgn * 1.0, sgn * 0.5)
-    return nbr, nrm, np.ones(n)
-
-
-def george_liu_passes(nbr) -> int:
-    """Breadth-first passes the pseudo-peripheral search of the oracle's
-    Cuthill-McKee takes on a connected graph whose lowest id is the start."""
-    def levels(r):
-        dist = -np.ones(nbr.shape[0], dtype=np.int64)
-        dist[r] = 0
-        q, h = [r], 0
-        while h < len(q):
-            v = q[h]
-            h += 1
-            for w in nbr[v]:
-                if dist[w] < 0:
-                    dist[w] = dist[v] + 1
-                    q.append(int(w))
-        return dist
-
-    def degree(v):
-        return len(set(int(x) for x in nbr[v]) - {v})
-
-    d = levels(0)
-    ecc, passes = int(d.max()), 1
-    while True:
-        last = np.flatnonzero(d == ecc)
-        pick = min(last, key=lambda v: (degree(v), v))
-        d2 = levels(pick)
-        passes += 1
-        if int(d2.max()) <= ecc:
-            return passes
-        d, ecc = d2, int(d2.max())
 
 
 @pytest.mark.parametrize("length,seed", [(40, 1), (301, 7)])

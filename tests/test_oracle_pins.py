@@ -136,3 +136,21 @@ def test_torch_reference_matches_oracle(o):
     got = torch_ref.rollout(torch_ref.Mesh(m.nbr, m.nrm, m.area), torch.from_numpy(U0), dt, 10)
     err = np.max(np.abs(got.numpy() - ref), axis=0) / np.max(np.abs(ref), axis=0)
     assert np.all(err <= 1e-14), err
+
+
+def test_ladder_search_moves_as_the_helper_counts():
+    """The ladder graph of the GPU test of a moving pseudo-peripheral search:
+    the helper's George-Liu pass count is 3 (the eccentricity grows once) and
+    its final root is the oracle's Cuthill-McKee root."""
+    from gpu_helpers import george_liu_passes, ladder_graph
+
+    nbr, _, _ = ladder_graph(40)
+    rng = np.random.default_rng(1)
+    p0 = rng.permutation(nbr.shape[0])
+    inv0 = np.empty_like(p0)
+    inv0[p0] = np.arange(p0.size)
+    nbr = inv0[nbr[p0]].astype(np.int32)
+    assert george_liu_passes(nbr) == 3
+    root = int(oracle.cm_order(nbr)[0])
+    # an end cell of the ladder (degree 2 through the doubled rung)
+    assert len(set(int(x) for x in nbr[root])) == 2
