@@ -51,7 +51,10 @@ constexpr int kPer = 3;             // frontier cells per thread and sweep
 
 typedef int i4v __attribute__((ext_vector_type(4)));  // a record as one register tuple
 
-// Block-wide exclusive scan over 1024 threads; *total receives the sum.
+// Block-wide exclusive scan over 1024 threads; *total receives the sum.  One
+// barrier: after it every wave scans the 16 wave totals itself.  sh must not
+// be written again before every thread has returned (the callers place a
+// barrier between two scans).
 __device__ __forceinline__ int block_exclusive_scan(int x, int *sh, int *total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -65,25 +68,17 @@ __device__ __forceinline__ int block_exclusive_scan(int x, int *sh, int *total)
     if (lane == 63)
         sh[wid] = incl;
     __syncthreads();
-    if (wid == 0) {
-        const int w = lane < kCmWaves ? sh[lane] : 0;
-        int wi = w;
+    const int t = lane < kCmWaves ? sh[lane] : 0;
+    int ti = t;
 #pragma unroll
-        for (int d = 1; d < kCmWaves; d <<= 1) {
-            const int y = __shfl_up(wi, d, 64);
-            if (lane >= d)
-                wi += y;
-        }
-        if (lane < kCmWaves)
-            sh[kCmWaves + lane] = wi - w;
-        if (lane == kCmWaves - 1)
-            sh[2 * kCmWaves] = wi;
+    for (int d = 1; d < kCmWaves; d <<= 1) {
+        const int y = __shfl_up(ti, d, 64);
+        if (lane >= d)
+            ti += y;
     }
-    __syncthreads();
-    const int excl = incl - x + sh[kCmWaves + wid];
-    *total = sh[2 * kCmWaves];
-    __syncthreads();
-    return excl;
+    const int wave_offset = __shfl(ti - t, wid, 64);
+    *total = __shfl(ti, kCmWaves - 1, 64);
+    return incl - x + wave_offset;
 }
 
 // Block-wide minimum of a 64-bit key over 1024 threads (all threads get it).
