@@ -50,7 +50,7 @@ STEP_SOURCE = os.path.join(ROOT, "paper_1408_5715_amd", "csrc", "fv_step.hip")
 MEASURED_TRAFFIC = {
     "source_sha": "02f9e3bbb22d696456438d6eaa9d030eb978559f05820e45870a06d81af9a197",
     "cells": 2097152,
-    "bytes_per_launch": 202402695,  # fetch 135,295,826 + write 67,106,869
+    "bytes_per_launch": 202403534,  # fetch 135,295,762 + write 67,107,772
 }
 
 
