@@ -270,7 +270,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(the step would shard by contiguous ranges of the renumbered order with a "
               "halo exchange per step; that exchange is not implemented).", file=sys.stderr)
         return 2

@@ -4,21 +4,22 @@
 # every step launch runs on the renumbered mesh): a kernel trace with per-kernel statistics, then one
 # counter pass each for FETCH_SIZE and WRITE_SIZE, with a plain 256 MiB copy
 # in the same run as the calibration, then L2 hits and misses of the step on
-# the random order and on the renumbered order.  Output: gpurun_out/prof_* under the
-# repository root.  Summarise with: python -m paper_1408_5715_amd.profile_summary
+# the random order and on the renumbered order.  Output: prof_* under
+# $FV_PROFILE_DIR (default: profile_out/ at the repository root).  Summarise
+# with: python -m paper_1408_5715_amd.profile_summary (same FV_PROFILE_DIR)
 #
 # `profile.sh learned`: the same three runs for the learned-correction
 # kernels (paper_1408_5715_amd/profile_learned.py: 20 corrected steps on the
 # 1024 x 1024 mesh, 4 corrected adjoint steps on the 32-flow training batch),
-# with MFMA counters in place of the byte counters.  Output gpurun_out/lprof_*.
+# with MFMA counters in place of the byte counters.  Output lprof_*.
 #
 # `profile.sh renumber`: two counter passes (wave and instruction counters;
 # texture-addresser, L1-to-L2 and clock counters) over one bench.py job of
 # the 2,097,152-cell workload, for the renumbering kernels and the step.
-# Output gpurun_out/rprof_*.  Summarise with profile_summary.py renumber.
+# Output rprof_*.  Summarise with profile_summary.py renumber.
 set -euo pipefail
 ROOT="$(cd "$(dirname "$0")/.." && pwd)"
-OUT="$ROOT/gpurun_out"
+OUT="${FV_PROFILE_DIR:-$ROOT/profile_out}"
 mkdir -p "$OUT"
 export TMPDIR=/tmp
 export PYTHONPATH="$ROOT${PYTHONPATH:+:$PYTHONPATH}"

@@ -1,7 +1,8 @@
 """Summarise the rocprofv3 output of profile.sh as Markdown.
 
-Reads gpurun_out/prof_trace (kernel trace + stats), gpurun_out/prof_fetch
-and gpurun_out/prof_write (FETCH_SIZE / WRITE_SIZE per dispatch).  Byte
+Reads prof_trace (kernel trace + stats), prof_fetch and prof_write
+(FETCH_SIZE / WRITE_SIZE per dispatch) under $FV_PROFILE_DIR (default:
+profile_out/ at the repository root), as profile.sh writes them.  Byte
 counters are scaled by what they read for the plain copy kernel in the same
 run (256 MiB read and 256 MiB written per launch).
 """
@@ -14,7 +15,7 @@ import statistics as st
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-OUT = os.path.join(ROOT, "gpurun_out")
+OUT = os.environ.get("FV_PROFILE_DIR", os.path.join(ROOT, "profile_out"))
 COPY_BYTES = 256 * 2**20
 CELLS = 2097152
 SIMDS = 1024  # 256 CUs x 4; SQ_VALU_MFMA_BUSY_CYCLES sums over them
