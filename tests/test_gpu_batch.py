@@ -11,7 +11,7 @@ import oracle
 import paper_1408_5715_amd as fv
 from fvgen import ic
 from fvgen.mesh import periodic_mesh, permute_mesh, random_permutation
-from gpu_helpers import TOL, log, rel_err, vortex_case
+from gpu_helpers import TOL, george_liu_passes, ladder_graph, log, rel_err, vortex_case
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +82,41 @@ def test_batch_equals_single_meshes(torch, order):
         m = parts[k]
         ref = oracle.step(m.nbr, m.nrm, m.area, Us[k], dts[k], 60)
         assert np.all(rel_err(got[begin[k]:begin[k + 1]], ref) <= TOL)
+
+
+def test_batch_renumbering_with_moving_searches(torch):
+    """A batch of two shuffled ladders (whose pseudo-peripheral search moves,
+    so their confirming pass on the renamed graph sees the eccentricity grow
+    and the search continues on the original graph) around a periodic mesh
+    (whose search stops after the confirmation): every mesh gets its own
+    sequential Cuthill-McKee order, with the pass counts that implies."""
+    meshes = []
+    for length, seed in ((40, 1), (301, 7)):
+        nbr, nrm, area = ladder_graph(length)
+        rng = np.random.default_rng(seed)
+        p0 = rng.permutation(nbr.shape[0])
+        inv0 = np.empty_like(p0)
+        inv0[p0] = np.arange(p0.size)
+        meshes.append((inv0[nbr[p0]].astype(np.int32), nrm[p0], area[p0]))
+    m, _, _ = vortex_case(9, perm_seed=4)
+    meshes.insert(1, (m.nbr, m.nrm, m.area))
+    begin = np.concatenate([[0], np.cumsum([x[0].shape[0] for x in meshes])]).astype(np.int64)
+    nbr = np.concatenate([x[0] + b for x, b in zip(meshes, begin)]).astype(np.int32)
+    nrm = np.concatenate([x[1] for x in meshes])
+    area = np.concatenate([x[2] for x in meshes])
+    log(f"batch with moving searches: {begin[-1]} cells")
+    s = fv.Solver(nbr, nrm, area, mesh_begin=begin)
+    try:
+        perm = s.renumber(fv.FV_ORDER_CM)
+        passes = s.renumber_passes()
+    finally:
+        s.close()
+    for k, x in enumerate(meshes):
+        lo, hi = begin[k], begin[k + 1]
+        assert np.array_equal(perm[lo:hi] - lo, oracle.cm_order(x[0])), f"mesh {k}"
+        gl = george_liu_passes(x[0])
+        # a search that moves counts its confirming pass once more
+        assert passes[k] == (gl + 1 if gl > 2 else gl), (k, passes[k], gl)
 
 
 @pytest.mark.parametrize("block", [128, 256, 512])
