@@ -54,8 +54,8 @@ typedef int32_t fv_status;
 
 /*
  * Device bytes the arena passed to fv_create must hold for n_cells cells
- * (about 256 bytes per cell).  Returns 0 if n_cells <= 0 or too large for
- * 32-bit cell indices.
+ * (about 288 bytes per cell plus 13 MB of fixed tables).  Returns 0 if
+ * n_cells <= 0 or too large for 32-bit cell indices.
  */
 size_t fv_arena_bytes(int64_t n_cells);
 
