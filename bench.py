@@ -13,9 +13,13 @@ the mesh and the initial state already resident in device memory:
 
 value = cells x 1000 / job time (cell updates per second, whole job).
 Also reported: the step kernel alone (HIP events over its 1000 launches on
-the library's stream) against the HBM roofline, the same kernel on the
-random (not renumbered) order, and the CPU oracle timed on a bounded sample
-of the same job.
+the library's stream) against the HBM roofline at 132 algorithmic bytes per
+cell update (and at the 96 bytes of the library's compact layout), the
+counter bytes per launch from the committed profile, the same kernel on a
+2048 x 2048-quad mesh whose working set is beyond the Infinity Cache, the
+kernel on the random (not renumbered) order, and the CPU oracle timed on a
+bounded sample of the same job on every core of the host's share (and on
+one core).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--fv-steps 1000]
 """
@@ -33,25 +37,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic HBM bytes of one cell update come from the library
-# (fv_bytes_per_update): each per-cell array touched once, the three
-# neighbour states counted as the cache reuse the renumbering provides.
-# General layout: read U 32 + neighbour ids 12 + normals 48 + 1/area 8,
-# write U 32 = 132; with 16-bit neighbour offsets and the derived third
-# normal 112; with, in addition, the two stored normals in 32-bit fixed point
-# (the layout of this workload after renumbering) 96.
+# Algorithmic HBM bytes of one cell update (section 8(d) accounting of the
+# path): read U 32 + neighbour ids 3 x 4 + normals 3 x 2 x 8 + 1/area 8,
+# write U 32 = 132 bytes; the three neighbour states count as the cache reuse
+# the renumbering provides.  `roofline.achieved` and `frac` use these bytes.
+# The library stores the renumbered mesh more compactly (16-bit neighbour
+# offsets, the third normal derived, two normals in 32-bit fixed point:
+# 96 bytes, fv_bytes_per_update); that layout's figures are reported beside
+# them (`layout_*`).
+ALG_BYTES_PER_UPDATE = 132
 HBM_PEAK_GBS = 8000.0
 STEP_SOURCE = os.path.join(ROOT, "paper_1408_5715_amd", "csrc", "fv_step.hip")
-
-# HBM traffic of one step launch on this workload (renumbered order, 96-byte
-# layout), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs, each scaled
-# by what the counter reads for a plain 256 MiB copy in the same run (x2.000
-# and x1.000).  Valid only for the step kernel source with this SHA-256.
-MEASURED_TRAFFIC = {
-    "source_sha": "02f9e3bbb22d696456438d6eaa9d030eb978559f05820e45870a06d81af9a197",
-    "cells": 2097152,
-    "bytes_per_launch": 202403534,  # fetch 135,295,762 + write 67,107,772
-}
+# HBM traffic of one step launch on the 1024 x 1024 workload, measured by the
+# FETCH_SIZE and WRITE_SIZE counter runs of profile.sh and written by
+# profile_summary.py into this file as a `traffic-record` line, with the
+# SHA-256 of the step kernel's source it was measured with.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fv_step_c2_counters.md")
 
 
 def log(msg: str) -> None:
@@ -63,48 +64,135 @@ def source_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
+def measured_traffic(cells: int):
+    """Counter bytes per step launch from TRAFFIC_FILE, or None when the file
+    has no record for this mesh size or the step kernel changed since."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic-record: "):
+            rec = json.loads(line[len("traffic-record: "):])
+            if rec.get("source_sha256") == source_sha() and rec.get("cells") == cells:
+                return rec
+    return None
+
+
+def cpu_threads() -> int:
+    """Host threads the CPU baseline may use: OMP_NUM_THREADS when set (the
+    share of the host given to this job), else the cores this process may
+    run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
 def cpu_baseline(m, U0, dt, fv_steps: int, sample_steps: int) -> dict:
-    """The oracle as it stands, single-threaded: CM order of the random-order
-    mesh plus sample_steps steps on the renumbered mesh, scaled to the job."""
+    """The oracle as it stands on this host: its Cuthill-McKee order of the
+    random-order mesh (sequential code) plus sample_steps steps on the
+    renumbered mesh with the cell loop on every available core, scaled to the
+    job; beside it the same steps on one core, and on the random order."""
     import numpy as np
 
     import oracle
     from fvgen.mesh import permute_mesh
 
+    threads = cpu_threads()
     t0 = time.perf_counter()
     perm = oracle.cm_order(m.nbr)
     t_cm = time.perf_counter() - t0
     mc = permute_mesh(m, perm.astype(np.int64))
     Uc = U0[perm]
     t0 = time.perf_counter()
-    oracle.step(mc.nbr, mc.nrm, mc.area, Uc, dt, sample_steps)
-    t_step = (time.perf_counter() - t0) / sample_steps
-    # the same steps on the random order: the CPU side of the renumbering
-    # comparison (section 7.2 measures 3-15 % on one core)
-    rnd = max(1, sample_steps // 4)
+    _, used = oracle.step_threads(mc.nbr, mc.nrm, mc.area, Uc, dt, sample_steps, threads)
+    t_all = (time.perf_counter() - t0) / sample_steps
+    one = max(2, sample_steps // 8)
+    t0 = time.perf_counter()
+    oracle.step(mc.nbr, mc.nrm, mc.area, Uc, dt, one)
+    t_one = (time.perf_counter() - t0) / one
+    # one core on the random order: the CPU side of the renumbering comparison
+    # (section 7.2 measures 3-15 % on one core)
+    rnd = max(1, one // 2)
     t0 = time.perf_counter()
     oracle.step(m.nbr, m.nrm, m.area, U0, dt, rnd)
     t_rnd = (time.perf_counter() - t0) / rnd
-    job = t_cm + fv_steps * t_step
-    cpu_model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
-                             "")
-    except OSError:
-        pass
+    job = t_cm + fv_steps * t_all
     return {
         "value": m.n * fv_steps / job,
         "unit": "cell-updates/s",
-        "cores": 1,
+        "cores": used,
         "kind": "oracle",
-        "sample": (f"oracle Cuthill-McKee order of the {m.n}-cell mesh ({t_cm:.2f} s) plus "
-                   f"{sample_steps} oracle steps on the renumbered mesh ({t_step:.3f} s/step), "
-                   f"scaled to the {fv_steps}-step job"),
-        "step_only_value": m.n / t_step,
-        "random_order_s_per_step": t_rnd,
-        "renumbered_s_per_step": t_step,
-        "cpu_model": cpu_model,
+        "sample": (f"oracle Cuthill-McKee order of the {m.n}-cell mesh ({t_cm:.2f} s, sequential) "
+                   f"plus {sample_steps} oracle steps on the renumbered mesh with the cell loop "
+                   f"on {used} threads ({t_all * 1e3:.1f} ms/step), scaled to the "
+                   f"{fv_steps}-step job; {one} steps on one core; {rnd} on the random order"),
+        "step_only_value": m.n / t_all,
+        "one_core": {"value": m.n * fv_steps / (t_cm + fv_steps * t_one),
+                     "step_only_value": m.n / t_one,
+                     "renumbered_s_per_step": t_one,
+                     "random_order_s_per_step": t_rnd},
+        "host_cpus": os.cpu_count(),
+        "cpu_model": cpu_model(),
+    }
+
+
+def hbm_resident_step(dev, N: int, fv_steps: int) -> dict:
+    """The step kernel on an N x N-quad mesh whose working set is far beyond
+    the 256 MB Infinity Cache (N = 2048: 8,388,608 cells, about 0.8 GB read
+    and written per step), renumbered: HIP events over fv_steps launches."""
+    import torch
+
+    import paper_1408_5715_amd as fv
+    from fvgen import ic
+    from fvgen.mesh import periodic_mesh, permute_mesh, random_permutation
+
+    log(f"HBM-resident case: generating the {N}x{N}-quad mesh")
+    m = permute_mesh(periodic_mesh(N, seed=1), random_permutation(2 * N * N, 2))
+    P = ic.bumps_primitive(m.centroid, seed=3)
+    U0 = ic.to_conserved(P)
+    dt = ic.cfl_dt(P, m.area, m.perimeter, 0.4)
+    s = fv.Solver(m.nbr, m.nrm, m.area, device=dev)
+    try:
+        ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+        a, b = ev(), ev()
+        a.record(s.stream)
+        fv.fv_renumber(s.ctx, fv.FV_ORDER_CM)
+        b.record(s.stream)
+        torch.cuda.synchronize()
+        renum_ms = a.elapsed_time(b)
+        s.upload_state(U0)
+        fv.fv_step(s.ctx, 20, dt)
+        a, b = ev(), ev()
+        a.record(s.stream)
+        fv.fv_step(s.ctx, fv_steps, dt)
+        b.record(s.stream)
+        torch.cuda.synchronize()
+        t = a.elapsed_time(b) * 1e-3 / fv_steps
+        layout = fv.fv_bytes_per_update(s.ctx)
+    finally:
+        s.close()
+    achieved = ALG_BYTES_PER_UPDATE * m.n / t / 1e9
+    return {
+        "workload": (f"periodic jittered {N}x{N}-quad mesh ({m.n} cells), renumbered on the GPU, "
+                     f"bump state; {fv_steps} steps"),
+        "cells": m.n,
+        "step_us": t * 1e6,
+        "cell_updates_per_s": m.n / t,
+        "achieved": achieved,
+        "frac": achieved / HBM_PEAK_GBS,
+        "layout_bytes_per_cell_update": layout,
+        "layout_achieved": layout * m.n / t / 1e9,
+        "renumber_ms": renum_ms,
     }
 
 
@@ -170,9 +258,12 @@ def bench_batch(args, dev) -> int:
                                 f"{n} cells), {fv_steps} FP64 steps per run, per-mesh dt"),
                    "cells": n, "meshes": len(parts), "fv_steps": fv_steps},
         "roofline": {"bound": "hbm", "kernel": "fv_step_kernel",
-                     "achieved": bpu * n * fv_steps / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": bpu * n * fv_steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_cell_update": bpu},
+                     "achieved": ALG_BYTES_PER_UPDATE * n * fv_steps / (ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ALG_BYTES_PER_UPDATE * n * fv_steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_cell_update": ALG_BYTES_PER_UPDATE,
+                     "layout_bytes_per_cell_update": bpu,
+                     "layout_achieved": bpu * n * fv_steps / (ms * 1e-3) / 1e9},
         "launch": {k: tuned[k] for k in ("block", "grid", "graph")},
         "breakdown": {"renumber_ms": renum_ms, "renumber_passes_max": int(passes.max()),
                       "step_us": ms * 1e3 / fv_steps},
@@ -256,7 +347,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1, help="untimed jobs")
     ap.add_argument("--fv-steps", type=int, default=1000, help="time steps per job")
     ap.add_argument("--N", type=int, default=1024, help="quads per side")
-    ap.add_argument("--cpu-sample-steps", type=int, default=100)
+    ap.add_argument("--cpu-sample-steps", type=int, default=200,
+                    help="oracle steps of the all-core CPU sample (one core runs 1/8 of them)")
+    ap.add_argument("--hbm-N", type=int, default=2048,
+                    help="quads per side of the HBM-resident step timing (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-random", action="store_true",
                     help="skip timing the step on the random (not renumbered) order")
@@ -334,14 +428,14 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    bytes_per_update = fv.fv_bytes_per_update(s.ctx)
+    layout_bytes = fv.fv_bytes_per_update(s.ctx)
     renum_ms = [a.elapsed_time(b) for a, b, _, _ in marks]
     step_ms = [b.elapsed_time(c) for _, b, c, _ in marks]
     down_ms = [c.elapsed_time(d) for _, _, c, d in marks]
     ms_per_job = wall * 1e3 / args.steps
     value = n * args.fv_steps * args.steps / wall
     step_kernel_s = float(np.mean(step_ms)) * 1e-3 / args.fv_steps
-    achieved = bytes_per_update * n / step_kernel_s / 1e9
+    achieved = ALG_BYTES_PER_UPDATE * n / step_kernel_s / 1e9
 
     # the same kernel on the random (identity) order, for the locality effect
     random_step_s = float("nan")
@@ -359,6 +453,7 @@ def main() -> int:
         torch.cuda.synchronize()
         random_step_s = a.elapsed_time(b) * 1e-3 / args.fv_steps
     s.close()
+    del dU0, dout
 
     if args.probe_copy:
         # known traffic: 256 MiB read and 256 MiB written per launch
@@ -367,11 +462,15 @@ def main() -> int:
         for _ in range(3):
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
+        del src, dst
 
-    traffic = None
-    if MEASURED_TRAFFIC is not None and MEASURED_TRAFFIC.get("source_sha") == source_sha() \
-            and MEASURED_TRAFFIC.get("cells") == n:
-        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+    hbm = None
+    if args.hbm_N > 0:
+        hbm = hbm_resident_step(dev, args.hbm_N, 200)
+        torch.cuda.empty_cache()
+
+    trec = measured_traffic(n)
+    traffic = None if trec is None else trec["fetch_bytes"] + trec["write_bytes"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -408,9 +507,16 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "bytes_per_cell_update": bytes_per_update,
+            "traffic_source": None if trec is None else os.path.relpath(TRAFFIC_FILE, ROOT),
+            "bytes_per_cell_update": ALG_BYTES_PER_UPDATE,
             "avg_launch_us": step_kernel_s * 1e6,
+            "layout_bytes_per_cell_update": layout_bytes,
+            "layout_achieved": layout_bytes * n / step_kernel_s / 1e9,
+            "layout_frac": layout_bytes * n / step_kernel_s / 1e9 / HBM_PEAK_GBS,
+            "note": ("the 1024x1024 working set (about 200 MB) fits in the 256 MB Infinity Cache; "
+                     "hbm_resident times the same kernel on a mesh beyond it"),
         },
+        "hbm_resident": hbm,
         "cpu_baseline": cpu,
         "breakdown": {
             "renumber_and_upload_ms": float(np.median(renum_ms)),

@@ -52,15 +52,20 @@ typedef int32_t fv_status;
 
 #define FV_CORRECTION_PARAMS 5252
 
+/* Largest mesh (cells) a context accepts: device offsets such as 6 n + i are
+ * formed in 32-bit integers.  About 77 GB of arena at this size. */
+#define FV_MAX_CELLS 268431360
+
 /*
  * Device bytes the arena passed to fv_create must hold for n_cells cells
  * (about 288 bytes per cell plus 13 MB of fixed tables).  Returns 0 if
- * n_cells <= 0 or too large for 32-bit cell indices.
+ * n_cells <= 0 or n_cells > FV_MAX_CELLS.
  */
 size_t fv_arena_bytes(int64_t n_cells);
 
 /*
- * Create a context for a mesh of n_cells triangles (section 6.2.1).
+ * Create a context for a mesh of n_cells triangles (section 6.2.1),
+ * 1 <= n_cells <= FV_MAX_CELLS.
  *   gamma       ratio of specific heats (the paper uses 1.4; section 6.1);
  *               must be finite and > 1.
  *   d_arena     device pointer, 256-byte aligned, >= fv_arena_bytes(n_cells);
@@ -235,14 +240,18 @@ fv_status fv_restrict(const double *d_src, int64_t n_src, const int32_t *d_idx, 
 fv_status fv_set_launch(fv_ctx *ctx, int32_t block, int32_t grid, int32_t use_graph);
 
 /*
- * Number of labelling passes (breadth-first sweeps of section 4's
+ * Number of breadth-first passes (level structures of section 4's
  * renumbering, including the pseudo-peripheral search) each mesh took in the
  * last fv_renumber with FV_ORDER_CM.  The search's second sweep over a mesh's
  * first component runs on a copy of the graph renamed by the first sweep's
- * labels (same eccentricity, better memory locality); when that eccentricity
- * is larger, the search repeats the sweep on the original graph, so such a
- * mesh counts one pass more than the sequential search takes.
+ * breadth-first order (same eccentricity, better memory locality); if the
+ * eccentricity does not grow, the labels follow from the first sweep's
+ * levels and the mesh counts 2 passes; if it grows, the search repeats that
+ * sweep as a labelling pass on the uploaded graph, so such a mesh counts one
+ * pass more than the sequential search takes.
  *   passes  host int32 [n_meshes].  Synchronises the stream.
+ * FV_ESTATE if no FV_ORDER_CM renumbering ran since the mesh was uploaded
+ * (or the last renumbering was FV_ORDER_IDENTITY).
  */
 fv_status fv_renumber_passes(fv_ctx *ctx, int32_t *passes);
 

@@ -32,6 +32,8 @@ class Oracle:
         L.oracle_cell_residual.restype = None
         L.oracle_step.argtypes = [i64, vp, vp, vp, dbl, dbl, i64, vp]
         L.oracle_step.restype = ctypes.c_int
+        L.oracle_step_threads.argtypes = [i64, vp, vp, vp, dbl, dbl, i64, vp, ctypes.c_int]
+        L.oracle_step_threads.restype = ctypes.c_int
         L.oracle_cm_order.argtypes = [i64, vp, vp]
         L.oracle_cm_order.restype = ctypes.c_int
         L.oracle_am1_order.argtypes = [i64, vp, vp]
@@ -73,6 +75,23 @@ class Oracle:
         if rc != 0:
             raise RuntimeError("oracle_step failed")
         return out
+
+    def step_threads(self, nbr, nrm, area, U, dt: float, n_steps: int, n_threads: int,
+                     gamma: float = 1.4):
+        """step() with each step's cell loop shared by n_threads OpenMP
+        threads (bitwise the same result); returns (U, threads used)."""
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        nrm = np.ascontiguousarray(nrm, dtype=np.float64)
+        area = np.ascontiguousarray(area, dtype=np.float64)
+        out = np.array(U, dtype=np.float64, order="C", copy=True)
+        n = nbr.shape[0]
+        if out.shape != (n, 4) or nrm.shape != (n, 3, 2) or area.shape != (n,):
+            raise ValueError("shape mismatch")
+        used = self.lib.oracle_step_threads(n, _p(nbr), _p(nrm), _p(area), float(gamma),
+                                            float(dt), int(n_steps), _p(out), int(n_threads))
+        if used < 1:
+            raise RuntimeError("oracle_step_threads failed")
+        return out, int(used)
 
     def cm_order(self, nbr) -> np.ndarray:
         """Cuthill-McKee permutation, new label -> old id."""
@@ -142,6 +161,10 @@ def cell_residual(*a, **k):
 
 def step(*a, **k):
     return default().step(*a, **k)
+
+
+def step_threads(*a, **k):
+    return default().step_threads(*a, **k)
 
 
 def cm_order(*a, **k):

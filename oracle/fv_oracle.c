@@ -47,6 +47,7 @@
  */
 
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -126,25 +127,32 @@ void oracle_cell_residual(int64_t i, const int32_t *nbr, const double *nrm, cons
  * n_steps forward-Euler steps (eqFWEuler and the update of section 6.2.2):
  * U_T^{n+1} = U_T^n - dt / V_T * sum_f R_{n_f} F_f |n_f|.
  * U is [n][4] (rho, rho u, rho v, E), updated in place; every step reads the
- * whole of U^n before any U^{n+1} value is used.
- * Returns 0, or -1 on a bad argument or allocation failure.
+ * whole of U^n before any U^{n+1} value is used.  With n_threads > 1 the
+ * cells of each step are shared among that many OpenMP threads (static
+ * schedule); every cell's update reads only U^n, so the result is bitwise the
+ * same.  Returns the number of threads that ran the cell loop, or -1 on a
+ * bad argument or allocation failure.
  */
-int oracle_step(int64_t n, const int32_t *nbr, const double *nrm, const double *area,
-                double gamma, double dt, int64_t n_steps, double *U)
+static int run_steps(int64_t n, const int32_t *nbr, const double *nrm, const double *area,
+                     double gamma, double dt, int64_t n_steps, double *U, int n_threads)
 {
-    if (n <= 0 || n_steps < 0 || !nbr || !nrm || !area || !U)
+    if (n <= 0 || n_steps < 0 || n_threads < 1 || !nbr || !nrm || !area || !U)
         return -1;
     double *Un = (double *)malloc((size_t)n * 4 * sizeof(double));
     if (!Un)
         return -1;
     double *cur = U, *nxt = Un;
+    int used = 1;
     for (int64_t s = 0; s < n_steps; ++s) {
+#pragma omp parallel for num_threads(n_threads) schedule(static) if (n_threads > 1)
         for (int64_t i = 0; i < n; ++i) {
             double R[4];
             oracle_cell_residual(i, nbr, nrm, cur, gamma, R);
             double coef = dt / area[i];
             for (int k = 0; k < 4; ++k)
                 nxt[4 * i + k] = cur[4 * i + k] - coef * R[k];
+            if (i == 0)
+                used = omp_get_num_threads();
         }
         double *t = cur;
         cur = nxt;
@@ -153,7 +161,24 @@ int oracle_step(int64_t n, const int32_t *nbr, const double *nrm, const double *
     if (cur != U)
         memcpy(U, cur, (size_t)n * 4 * sizeof(double));
     free(Un);
-    return 0;
+    return used;
+}
+
+/* The steps on the calling thread.  Returns 0, or -1 on a bad argument or
+ * allocation failure. */
+int oracle_step(int64_t n, const int32_t *nbr, const double *nrm, const double *area,
+                double gamma, double dt, int64_t n_steps, double *U)
+{
+    return run_steps(n, nbr, nrm, area, gamma, dt, n_steps, U, 1) < 0 ? -1 : 0;
+}
+
+/* The steps with the cell loop on n_threads OpenMP threads (timing the
+ * oracle on all the cores of a host).  Returns the number of threads used,
+ * or -1. */
+int oracle_step_threads(int64_t n, const int32_t *nbr, const double *nrm, const double *area,
+                        double gamma, double dt, int64_t n_steps, double *U, int n_threads)
+{
+    return run_steps(n, nbr, nrm, area, gamma, dt, n_steps, U, n_threads);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -390,53 +415,56 @@ int oracle_bandwidth(int64_t n, const int32_t *nbr, const int32_t *label, int64_
 
 
 /*
- * AM1's choice of the next node (section 4.2): the candidates are u(I), the
- * neighbours of node(I) not yet in the part, in increasing id; for each,
- * local_max is the largest imp(l) over its neighbours l in the part other
- * than node(I); the first candidate whose local_max exceeds every earlier
- * one (starting from 0) wins, else the first candidate.  pos[] holds part
- * positions (-1 outside), uc[] and sv[] |u()| and s() by position;
- * imp(l) = (size - 1 - l) + |u(l)| + s(l) for l >= I, 0 for l < I and for
+ * Importance of the part's node at position p (section 4.2):
+ * imp = (size - 1 - p) + |u(p)| + s(p) for p >= I, and 0 for p < I and for
  * ghost positions (ghost may be NULL).
+ */
+static int64_t am1_importance(int64_t p, int64_t I, int64_t size, const int64_t *uc,
+                              const int64_t *sv, const uint8_t *ghost)
+{
+    if (p < I || (ghost && ghost[p]))
+        return 0;
+    return (size - 1 - p) + uc[p] + sv[p];
+}
+
+/*
+ * AM1's next node (section 4.2): among u(I), the neighbours of node(I) not
+ * yet in the part, the vertex k whose most important neighbour in the part
+ * other than node(I) is most important,
+ *   score(k) = max { imp(l) : l a neighbour of k in the part, l != node(I) }
+ *              (0 when k has no such neighbour),
+ * taken as an argmax of (score, -id): equal scores go to the smaller id
+ * (the paper picks a random element of u(I) to start its search; reading
+ * R13 replaces it by the smallest id).  pos[] holds part positions (-1
+ * outside); uc[] and sv[] hold |u()| and s() by position.
  */
 static int64_t am1_candidate(const int32_t *nbr, int64_t vI, const int64_t *pos, int64_t I,
                              int64_t size, const int64_t *uc, const int64_t *sv,
                              const uint8_t *ghost)
 {
-    int32_t cnb[3];
-    const int cd = distinct_neighbours(nbr, vI, cnb);
-    int32_t cand[3] = {0, 0, 0};
-    int nc = 0;
-    for (int g = 0; g < cd; ++g)
-        if (pos[cnb[g]] < 0)
-            cand[nc++] = cnb[g];
-    for (int a1 = 1; a1 < nc; ++a1)
-        for (int b1 = a1; b1 > 0 && cand[b1 - 1] > cand[b1]; --b1) {
-            const int32_t t = cand[b1];
-            cand[b1] = cand[b1 - 1];
-            cand[b1 - 1] = t;
-        }
-    int64_t chosen = cand[0];
-    int64_t global_max = 0;
-    for (int c = 0; c < nc; ++c) {
+    int32_t around[3];
+    const int na = distinct_neighbours(nbr, vI, around);
+    int64_t best = -1, best_score = -1;
+    for (int a = 0; a < na; ++a) {
+        const int64_t k = around[a];
+        if (pos[k] >= 0)
+            continue; /* already in the part: not in u(I) */
         int32_t knb[3];
-        const int kd = distinct_neighbours(nbr, cand[c], knb);
-        int64_t local_max = 0;
+        const int kd = distinct_neighbours(nbr, k, knb);
+        int64_t score = 0;
         for (int g = 0; g < kd; ++g) {
             const int64_t p = pos[knb[g]];
-            if (p < 0 || knb[g] == vI)
-                continue;
-            const int64_t imp =
-                (p < I || (ghost && ghost[p])) ? 0 : (size - 1 - p) + uc[p] + sv[p];
-            if (imp > local_max)
-                local_max = imp;
+            if (p >= 0 && knb[g] != vI) {
+                const int64_t imp = am1_importance(p, I, size, uc, sv, ghost);
+                score = imp > score ? imp : score;
+            }
         }
-        if (local_max > global_max) {
-            chosen = cand[c];
-            global_max = local_max;
+        if (best < 0 || score > best_score || (score == best_score && k < best)) {
+            best = k;
+            best_score = score;
         }
     }
-    return chosen;
+    return best;
 }
 
 /*
@@ -449,11 +477,10 @@ static int64_t am1_candidate(const int32_t *nbr, int64_t vI, const int64_t *pos,
  *   u(i)  = its neighbours not yet in P;
  *   I     = first position whose u() is not empty;
  *   imp(i) = (|P| - 1 - i) + |u(i)| + s(i) for i >= I, 0 for i < I.
- * Each step takes the candidates k of u(I); for each, local_max is the
- * largest imp(l) over its neighbours l in P other than node(I); the first
- * candidate whose local_max exceeds every earlier one (starting from 0) is
- * appended, else the first candidate.  The part starts at the George-Liu
- * pseudo-peripheral root (section 4.2.2's pseudo-diameter endpoint).
+ * Each step appends the candidate k of u(I) whose most important neighbour
+ * in P other than node(I) has the largest imp(), the smaller id on ties
+ * (am1_candidate).  The part starts at the George-Liu pseudo-peripheral
+ * root (section 4.2.2's pseudo-diameter endpoint).
  * Returns 0, or -1 on a bad argument or allocation failure.
  */
 int oracle_am1_order(int64_t n, const int32_t *nbr, int32_t *perm_out)

@@ -13,6 +13,7 @@ from .fvgpu import (  # noqa: F401
     FV_ESTATE,
     FV_OK,
     FV_CORRECTION_PARAMS,
+    FV_MAX_CELLS,
     FV_ORDER_CM,
     FV_ORDER_IDENTITY,
     FVError,

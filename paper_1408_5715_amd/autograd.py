@@ -30,11 +30,17 @@ class Rollout(torch.autograd.Function):
         every = int(every) if every else n_steps
         if n_steps % every:
             raise ValueError("every must divide n_steps")
+        if isinstance(dt, (list, tuple, np.ndarray, torch.Tensor)):
+            raise ValueError("a rollout takes one dt for every mesh (the adjoint step has one)")
+        dt = float(dt)
+        p = None
         if params is not None:
-            p = params.detach().to("cpu", torch.float32).numpy()
+            p = params.detach().to("cpu", torch.float32).numpy().copy()
             if p.shape != (FV_CORRECTION_PARAMS,):
                 raise ValueError(f"params must have {FV_CORRECTION_PARAMS} values")
-            solver.set_correction(p)
+        # the rollout runs the plain step without params, whatever the
+        # solver held before; the backward sets the same correction again
+        solver.set_correction(p)
         fv_upload_state_device(solver.ctx, U0.contiguous())
         saved, outs = [], []
         for s in range(n_steps):
@@ -46,6 +52,7 @@ class Rollout(torch.autograd.Function):
         ctx.solver, ctx.n_steps, ctx.dt = solver, n_steps, dt
         ctx.checkpoint, ctx.every, ctx.saved = checkpoint, every, saved
         ctx.with_params = params is not None
+        ctx.params_host = p
         ctx.params_device = params.device if params is not None else None
         out = torch.stack(outs) if every != n_steps else outs[0]
         return out
@@ -58,6 +65,8 @@ class Rollout(torch.autograd.Function):
         lam = torch.zeros((s.n, 4), dtype=torch.float64, device=grad_out.device)
         gtheta = (torch.zeros(FV_CORRECTION_PARAMS, dtype=torch.float64, device=grad_out.device)
                   if ctx.with_params else None)
+        # the solver may have been given another correction since the forward
+        s.set_correction(ctx.params_host)
         starts = list(range(0, n, cp))
         for seg, start in reversed(list(enumerate(starts))):
             k = min(cp, n - start)
@@ -72,6 +81,7 @@ class Rollout(torch.autograd.Function):
                     lam += grads[(step + 1) // every - 1]
                 fv_step_adjoint_grad(s.ctx, states[i], lam, dt, gtheta)
         ctx.saved = None
+        ctx.params_host = None
         gp = None
         if ctx.with_params:
             gp = gtheta.to(ctx.params_device, torch.float32)
@@ -83,6 +93,7 @@ def rollout(U0, solver, n_steps: int, dt: float, checkpoint: int = 4, params=Non
     """States after a rollout of n_steps steps from U0 (float64 CUDA [n, 4],
     mesh numbering), differentiable with respect to U0 and, if given, the
     correction parameters (float32 [FV_CORRECTION_PARAMS], set on the solver
-    for the rollout).  every = 0: the final state; else the states after
+    for the rollout; without them the plain step runs).  dt is one time step
+    for every mesh of a batch.  every = 0: the final state; else the states after
     every `every` steps, stacked [n_steps / every, n, 4]."""
     return Rollout.apply(U0, params, solver, n_steps, dt, checkpoint, every)

@@ -87,12 +87,13 @@ hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *
 // Cuthill-McKee order of every segment [seg[k], seg[k+1]) (device array of
 // n_seg + 1 offsets; no face crosses a segment), one workgroup per segment:
 // perm[label] = cell, label[cell] = label.  rec comes fresh from
-// launch_build_records; rec2 (n records), state (n_seg entries), permA and
-// permB (n entries each) are scratch; passes[k] receives the number of
-// labelling passes of segment k.
-hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t n, int32_t n_seg,
-                              const int64_t *seg, int32_t *permA, int32_t *permB, int32_t *perm,
-                              int32_t *label, int32_t *passes, hipStream_t s);
+// launch_build_records; rec2 (n records), state and probe (n_seg entries
+// each), permA, permB and levA (n entries each) are scratch; passes[k]
+// receives the number of breadth-first passes of segment k.
+hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe, int32_t n,
+                              int32_t n_seg, const int64_t *seg, int32_t *permA, int32_t *permB,
+                              int32_t *levA, int32_t *perm, int32_t *label, int32_t *passes,
+                              hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_iota(int32_t *p, int32_t count, hipStream_t s);

@@ -299,7 +299,6 @@ __device__ __forceinline__ PassResult cm_pass(int4 *__restrict__ rec, int32_t ro
 {
     int4 (&frontier)[2][kFrontierCap] = lds.frontier;
     unsigned char (&known)[2][kFrontierCap] = lds.known;
-    int *scan_sh = lds.scan;
     unsigned long long *min_sh = lds.minv;
 
     int32_t *label = reinterpret_cast<int32_t *>(rec);  // label of cell v: label[4 v + 3]
@@ -369,56 +368,470 @@ __device__ __forceinline__ PassResult cm_pass(int4 *__restrict__ rec, int32_t ro
     return r;
 }
 
+// ---- breadth-first sweeps for the pseudo-peripheral search ---------------
+//
+// The George-Liu search needs only level structures (eccentricity and the
+// last level), which do not depend on the order inside a level, so a sweep
+// does not rank children by owner label.  A frontier cell fetches the records
+// of its neighbours not known to be visited; the record's fourth field marks
+// a visited cell (-1 while unvisited), so the same load that brings a cell's
+// neighbour list also says whether it is new.  A new cell proposed by
+// several frontier cells of one sweep is claimed by exactly one of them
+// through a hash set in LDS (an LDS compare-and-swap per proposal).  One
+// round of scattered memory traffic per level, and no global atomics (which
+// serialise where neighbouring cells share a cache line).
+
+constexpr int kBfsCap = 3584;         // frontier entries held in LDS per buffer
+constexpr int kHashSlots = 8192;      // > 2 * kCmThreads * kPer: the set never fills
+constexpr unsigned kHashEmpty = 0xffffffffu;
+static_assert(kHashSlots > 2 * kCmThreads * kPer, "hash set must outgrow a sweep's new cells");
+
+struct BfsLds {
+    int4 frontier[2][kBfsCap];          // (cell, nb_0, nb_1, nb_2) in breadth-first order
+    unsigned char known[2][kBfsCap];    // bit f: nb_f is the cell's discoverer
+    unsigned set[kHashSlots];           // cells claimed in the current sweep
+    int scan[2 * kCmWaves + 1];
+    unsigned long long minv[kCmWaves];
+};
+
+// Insert c into the LDS hash set; true if this call inserted it (claims c).
+// At most one sweep's new cells live in the set, fewer than kHashSlots, so an
+// empty slot is always reached; the loop is bounded by the table size.
+__device__ __forceinline__ bool claim(unsigned *set, int c)
+{
+    unsigned h = ((unsigned)c * 0x9E3779B1u) >> 19;  // 13 bits
+    for (int probe = 0; probe < kHashSlots; ++probe) {
+        const unsigned old = atomicCAS(set + h, kHashEmpty, (unsigned)c);
+        if (old == kHashEmpty)
+            return true;
+        if (old == (unsigned)c)
+            return false;
+        h = (h + 1) & (kHashSlots - 1);
+    }
+    return false;
+}
+
+// One sweep of a breadth-first level [a, b): frontier positions
+// [c0, c0 + span), P per thread.  New cells are appended from b + produced
+// on: ord[b + p] receives the p-th new cell, whose record's fourth field is
+// set to `mark` (its record is kept in LDS while p < kBfsCap).  Returns the
+// number of new cells (block-uniform).  The hash set must be empty on entry
+// and is empty again on return.  Called by all threads of the block.
+template <int P>
+__device__ __forceinline__ int bfs_sweep(int4 *__restrict__ graph, int32_t *__restrict__ ord,
+                                         BfsLds &lds, int cur, int a, int b, int c0, int span,
+                                         int produced, int mark)
+{
+    const int tid = threadIdx.x;
+    const int first = tid * P;
+    const bool wave_busy = (tid & ~63) * P < span;
+
+    int v[P], w[P][3];
+    unsigned won[P];  // bit f: this thread claimed w[k][f]
+    i4v rw[P][3];
+    int total = 0;
+    if (wave_busy) {
+        unsigned kn[P];
+        bool ok[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int t = first + k;
+            ok[k] = t < span;
+            const int ft = c0 + t;
+            const int slot = (ok[k] && ft < kBfsCap) ? ft : 0;
+            i4v e = reinterpret_cast<const i4v *>(lds.frontier[cur])[slot];
+            unsigned kb = lds.known[cur][slot];
+            asm volatile("" : "+v"(e), "+v"(kb));
+            kn[k] = kb;
+            if (ok[k] && ft >= kBfsCap) {
+                const int c = ord[a + ft];
+                const int4 r = graph[c];
+                e = i4v{c, r.x, r.y, r.z};
+                kn[k] = 0;
+            }
+            v[k] = e[0];
+            w[k][0] = e[1];
+            w[k][1] = e[2];
+            w[k][2] = e[3];
+        }
+        // records of the neighbours not known to be visited, all in flight
+        // together (the empty asm statements keep the uses out of the
+        // branches that load them)
+        const i4v *gv = reinterpret_cast<const i4v *>(graph);
+        bool cand[P][3];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const int ww = w[k][f];
+                cand[k][f] = ok[k] && !((kn[k] >> f) & 1u) && ww != v[k] &&
+                             !(f >= 1 && w[k][0] == ww) && !(f == 2 && w[k][1] == ww);
+                rw[k][f] = i4v{0, 0, 0, 0};
+                if (cand[k][f])
+                    rw[k][f] = gv[ww];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            won[k] = 0;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                i4v r = rw[k][f];
+                asm volatile("" : "+v"(r));
+                rw[k][f] = r;
+                if (cand[k][f] && r[3] == -1 && claim(lds.set, w[k][f]))
+                    won[k] |= 1u << f;
+            }
+            total += __builtin_popcount(won[k]);
+        }
+    }
+    int sweep_total;
+    int pos = produced + block_exclusive_scan(total, lds.scan, &sweep_total);
+    // every claim of this sweep is in: empty the set for the next sweep
+    // (the caller's barrier separates this from the next sweep's claims)
+    for (int t = tid; t < kHashSlots; t += kCmThreads)
+        lds.set[t] = kHashEmpty;
+    if (wave_busy) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                if ((won[k] >> f) & 1u) {
+                    const int c = w[k][f];
+                    const i4v r = rw[k][f];
+                    reinterpret_cast<int32_t *>(graph)[4 * c + 3] = mark;
+                    ord[b + pos] = c;
+                    if (pos < kBfsCap) {
+                        lds.frontier[cur ^ 1][pos] = make_int4(c, r[0], r[1], r[2]);
+                        lds.known[cur ^ 1][pos] = (unsigned char)((r[0] == v[k]) |
+                                                                  (r[1] == v[k]) << 1 |
+                                                                  (r[2] == v[k]) << 2);
+                    }
+                    ++pos;
+                }
+            }
+        }
+    }
+    return sweep_total;
+}
+
+struct BfsResult {
+    int count;  // cells reached (the component of the root)
+    int ecc;    // eccentricity of the root
+    int pick;   // last-level cell of minimum (degree, original id): its original id
+    int width;  // largest level
+};
+
+// Breadth-first level structure of the component of `root` in `graph`
+// (records (nb_0, nb_1, nb_2, mark), mark -1 for every cell of the
+// component on entry; reached cells are marked with their level).  ord[base
+// + p] receives the p-th cell reached (levels in order); lev, when not null,
+// receives lev[base + k] = the first position of level k.  orig, when not
+// null, gives the original id of a cell (else the cell index is its id).
+// Called by all threads of the block.
+__device__ __forceinline__ BfsResult bfs_pass(int4 *__restrict__ graph, int32_t root, int32_t base,
+                                              int32_t *__restrict__ ord, int32_t *__restrict__ lev,
+                                              const int32_t *__restrict__ orig, BfsLds &lds)
+{
+    const int tid = threadIdx.x;
+    for (int t = tid; t < kHashSlots; t += kCmThreads)
+        lds.set[t] = kHashEmpty;
+    if (tid == 0) {
+        const int4 r = graph[root];
+        reinterpret_cast<int32_t *>(graph)[4 * root + 3] = 0;
+        ord[base] = root;
+        lds.frontier[0][0] = make_int4(root, r.x, r.y, r.z);
+        lds.known[0][0] = 0;
+        if (lev)
+            lev[base] = base;
+    }
+    __threadfence_block();
+    __syncthreads();
+
+    int a = base, b = base + 1;
+    int cur = 0, ecc = 0, width = 1;
+    for (;;) {
+        const int F = b - a;
+        int produced = 0;
+        for (int c0 = 0; c0 < F; c0 += kCmThreads * kPer) {
+            const int span = min(F - c0, kCmThreads * kPer);
+            const int per = (span + kCmThreads - 1) / kCmThreads;
+            int st;
+            if (per == 1)
+                st = bfs_sweep<1>(graph, ord, lds, cur, a, b, c0, span, produced, ecc + 1);
+            else if (per == 2)
+                st = bfs_sweep<2>(graph, ord, lds, cur, a, b, c0, span, produced, ecc + 1);
+            else
+                st = bfs_sweep<3>(graph, ord, lds, cur, a, b, c0, span, produced, ecc + 1);
+            produced += st;
+            __threadfence_block();
+            __syncthreads();
+        }
+        if (produced == 0)
+            break;
+        ++ecc;
+        a = b;
+        b += produced;
+        width = max(width, produced);
+        if (lev && tid == 0)
+            lev[base + ecc] = a;
+        cur ^= 1;
+    }
+
+    unsigned long long best = ~0ull;
+    for (int t = tid; t < b - a; t += kCmThreads) {
+        int c;
+        int4 r;
+        if (t < kBfsCap) {
+            r = lds.frontier[cur][t];
+            c = r.x;
+            r = make_int4(r.y, r.z, r.w, 0);
+        } else {
+            c = ord[a + t];
+            r = graph[c];
+        }
+        const int d = degree_of(c, r.x, r.y, r.z);
+        const unsigned id = orig ? (unsigned)orig[c] : (unsigned)c;
+        const unsigned long long key = ((unsigned long long)d << 32) | id;
+        best = key < best ? key : best;
+    }
+    best = block_min_u64(best, lds.minv);
+    BfsResult res;
+    res.count = b - base;
+    res.ecc = ecc;
+    res.pick = (int32_t)(best & 0xffffffffu);
+    res.width = width;
+    return res;
+}
+
+// ---- Cuthill-McKee labels from a known level structure -------------------
+//
+// With the levels of the root known, level k+1 is labelled from level k
+// alone: a cell's parent is its neighbour of smallest label in level k, and
+// the labels of level k+1 follow (parent label, degree, original id).  The
+// cells of every level are contiguous in the renamed graph (positions of
+// the breadth-first order), so each level's records are one coalesced read,
+// issued a level ahead; parents, sibling ranks and the scan over parents
+// stay in LDS, and the barriers wait for LDS only, so the next level's
+// records stay in flight across them.
+
+constexpr int kLabelCap = 4096;  // widest level the labelling keeps in LDS
+
+struct LabelLds {
+    int lab[2][kLabelCap];        // labels of the previous / current level, by position
+    int cnt[2][kLabelCap];        // children per parent of the previous level
+    int first[kLabelCap];         // label offset of each parent's children
+    unsigned sib[3 * kLabelCap];  // (degree, original id) keys of each parent's children
+    int scan[2 * kCmWaves + 1];
+};
+
+// Barrier that orders LDS accesses only: global loads stay in flight.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// block_exclusive_scan with an LDS-only barrier.
+__device__ __forceinline__ int block_exclusive_scan_lds(int x, int *sh, int *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(incl, d, 64);
+        if (lane >= d)
+            incl += y;
+    }
+    if (lane == 63)
+        sh[wid] = incl;
+    lds_barrier();
+    const int t = lane < kCmWaves ? sh[lane] : 0;
+    int ti = t;
+#pragma unroll
+    for (int d = 1; d < kCmWaves; d <<= 1) {
+        const int y = __shfl_up(ti, d, 64);
+        if (lane >= d)
+            ti += y;
+    }
+    const int wave_offset = __shfl(ti - t, wid, 64);
+    *total = __shfl(ti, kCmWaves - 1, 64);
+    return incl - x + wave_offset;
+}
+
+// Labels of the component held at positions [base, base + count) of the
+// renamed graph g (neighbours as positions; orig[p] the original id of
+// position p), whose breadth-first levels from the root at position base are
+// [lev[base + k], lev[base + k + 1]) for k = 0..ecc (the last ending at
+// base + count), every level at most kLabelCap wide: perm[label] = original
+// id for labels [base, base + count).  Called by all threads of the block.
+__device__ __forceinline__ void label_levels(const int4 *__restrict__ g,
+                                             const int32_t *__restrict__ orig,
+                                             const int32_t *__restrict__ lev, int32_t base,
+                                             int32_t count, int32_t ecc,
+                                             int32_t *__restrict__ perm, LabelLds &lds)
+{
+    constexpr int kSlots = kLabelCap / kCmThreads;
+    const int tid = threadIdx.x;
+    const int end = base + count;
+    for (int t = tid; t < kLabelCap; t += kCmThreads) {
+        lds.cnt[0][t] = 0;
+        lds.cnt[1][t] = 0;
+    }
+    if (tid == 0) {
+        lds.lab[0][0] = base;
+        perm[base] = orig[base];
+    }
+    // records and original ids of level 1, positions [base + 1, hi)
+    int lo_prev = base, lo = base + 1;
+    int hi = ecc >= 2 ? lev[base + 2] : end;
+    int4 r[kSlots];
+    int id[kSlots];
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) {
+        const int q = lo + tid + j * kCmThreads;
+        r[j] = q < hi ? g[q] : make_int4(0, 0, 0, 0);
+        id[j] = q < hi ? orig[q] : 0;
+    }
+    lds_barrier();
+    for (int k = 0; k < ecc; ++k) {
+        // the next level's records, in flight while this level is labelled
+        const int hi2 = k + 3 <= ecc ? lev[base + k + 3] : end;
+        int4 rn[kSlots];
+        int idn[kSlots];
+#pragma unroll
+        for (int j = 0; j < kSlots; ++j) {
+            const int q = hi + tid + j * kCmThreads;
+            rn[j] = q < hi2 ? g[q] : make_int4(0, 0, 0, 0);
+            idn[j] = q < hi2 ? orig[q] : 0;
+        }
+        const int fp = lo - lo_prev;
+        const int *labp = lds.lab[k & 1];
+        int *labn = lds.lab[(k + 1) & 1];
+        int *cnt = lds.cnt[k & 1];
+        int par[kSlots];
+        unsigned key[kSlots];
+#pragma unroll
+        for (int j = 0; j < kSlots; ++j) {
+            const int q = lo + tid + j * kCmThreads;
+            par[j] = -1;
+            if (q < hi) {
+                int best = INT_MAX;
+                const int nb3[3] = {r[j].x, r[j].y, r[j].z};
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const int x = nb3[f];
+                    if (x >= lo_prev && x < lo) {
+                        const int l = labp[x - lo_prev];
+                        best = l < best ? l : best;
+                    }
+                }
+                par[j] = best - lo_prev;
+                key[j] = (unsigned)degree_of(q, r[j].x, r[j].y, r[j].z) << 30 | (unsigned)id[j];
+                const int slot = atomicAdd(&cnt[par[j]], 1);
+                lds.sib[3 * par[j] + slot] = key[j];
+            }
+        }
+        lds_barrier();
+        // exclusive scan of the children counts over the parents in label order
+        int c4[kSlots], sum = 0;
+#pragma unroll
+        for (int j = 0; j < kSlots; ++j) {
+            const int o = tid * kSlots + j;
+            c4[j] = o < fp ? cnt[o] : 0;
+            sum += c4[j];
+        }
+        int tot;
+        int off = block_exclusive_scan_lds(sum, lds.scan, &tot);
+#pragma unroll
+        for (int j = 0; j < kSlots; ++j) {
+            const int o = tid * kSlots + j;
+            if (o < fp)
+                lds.first[o] = off;
+            off += c4[j];
+        }
+        // the other parity's counts were last read a level ago: clear them
+        // for the next level
+        int *cnt_next = lds.cnt[(k + 1) & 1];
+        for (int t = tid; t < hi - lo; t += kCmThreads)
+            cnt_next[t] = 0;
+        lds_barrier();
+#pragma unroll
+        for (int j = 0; j < kSlots; ++j) {
+            const int q = lo + tid + j * kCmThreads;
+            if (q < hi) {
+                const int pa = par[j];
+                const int nc = cnt[pa];
+                int rank = 0;
+                for (int u = 0; u < nc; ++u)
+                    rank += lds.sib[3 * pa + u] < key[j];
+                const int l = lo + lds.first[pa] + rank;
+                labn[q - lo] = l;
+                perm[l] = id[j];
+            }
+        }
+        lds_barrier();
+        lo_prev = lo;
+        lo = hi;
+        hi = hi2;
+#pragma unroll
+        for (int j = 0; j < kSlots; ++j) {
+            r[j] = rn[j];
+            id[j] = idn[j];
+        }
+    }
+}
+
 // Cuthill-McKee order of each segment [seg[s], seg[s+1]), one workgroup per
 // segment (no face may cross a segment boundary).  Within a segment,
 // components are taken in order of their lowest id; each one's root is found
-// by the George-Liu search from that id (label from the current root, take
-// the last level's cell of minimum (degree, id), relabel from it, keep it
-// while the eccentricity grows).  Output perm[label] = cell; permA and permB
-// are scratch of n entries.  A cell's record label is -1 until the first
-// pass reaches it, so the next component's root is the lowest cell still at
-// -1.
+// by the George-Liu search from that id (level structure from the current
+// root, take the last level's cell of minimum (degree, id), move to it while
+// the eccentricity grows).  Output perm[label] = cell.
 //
-// The search's second pass over the first component usually only confirms
-// that the eccentricity does not grow, and level sets do not depend on the
-// order inside a level.  So that pass runs on a copy of the component's
-// graph renamed by the first pass's labels (rec2, built by
-// cm_translate_kernel), whose records lie far closer together in memory than
-// those of an arbitrary input order; only its eccentricity is used.  If it
-// exceeds the first pass's, the search continues exactly as above on the
-// original graph (where ties between children are broken by the original
-// ids).
+// The first component of a segment (every cell, for a connected mesh) takes
+// the fast route:
+//   cm_first_kernel      breadth-first sweep from the segment's lowest id on
+//                        the uploaded graph: its order (ordA), level starts
+//                        (levA), eccentricity and pick; reached cells are
+//                        marked in their records;
+//   cm_invert_kernel,    the component's graph renamed by that order (rec2:
+//   cm_rename_kernel     neighbours as positions), in which every level is a
+//                        contiguous range;
+//   cm_probe_kernel      two workgroups per segment, side by side: the sweep
+//                        from the pick on rec2 (the search's second step),
+//                        and the labels from the first sweep's levels
+//                        (label_levels), which are the result when the
+//                        eccentricity does not grow (the root then stays
+//                        the lowest id);
+//   cm_finish_kernel     otherwise, and for every later component, the
+//                        search continues with full labelling passes on the
+//                        uploaded graph (cm_pass).
 //
-// cm_first_kernel: the first pass of every segment (root: the segment's
-// lowest cell, into permA); state[s] = (cells labelled, eccentricity, pick).
+// cm_first_kernel: state[s] = (cells reached, eccentricity, pick, widest level).
 __global__ __launch_bounds__(kCmThreads) void cm_first_kernel(int4 *__restrict__ rec,
                                                               const int64_t *__restrict__ seg,
-                                                              int32_t *__restrict__ permA,
+                                                              int32_t *__restrict__ ordA,
+                                                              int32_t *__restrict__ levA,
                                                               int4 *__restrict__ state)
 {
-    __shared__ PassLds lds;
+    __shared__ BfsLds lds;
     const int s0 = (int)seg[blockIdx.x], s1 = (int)seg[blockIdx.x + 1];
     if (s0 >= s1) {  // block-uniform; uploads reject empty segments
         if (threadIdx.x == 0)
             state[blockIdx.x] = make_int4(0, 0, s0, 0);
         return;
     }
-    const PassResult r = cm_pass(rec, s0, s0, permA, lds);
+    const BfsResult r = bfs_pass(rec, s0, s0, ordA, levA, nullptr, lds);
     if (threadIdx.x == 0)
-        state[blockIdx.x] = make_int4(r.count, r.ecc, r.pick, 0);
+        state[blockIdx.x] = make_int4(r.count, r.ecc, r.pick, r.width);
 }
 
-// rec2[l] = (labels of the three neighbours of the cell labelled l, -1) for
-// every label l of a segment's first component (labels from the first pass,
-// which are also the positions in rec2); other positions are left alone.
-__global__ void cm_translate_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict__ seg,
-                                    const int4 *__restrict__ state, const int4 *__restrict__ rec,
-                                    const int32_t *__restrict__ permA, int4 *__restrict__ rec2)
+// Segment of position l: the last s with seg[s] <= l.
+__device__ __forceinline__ int segment_of(int l, int n_seg, const int64_t *__restrict__ seg)
 {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= n)
-        return;
-    int lo = 0, hi = n_seg - 1;  // segment of l: the last s with seg[s] <= l
+    int lo = 0, hi = n_seg - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (seg[mid] <= l)
@@ -426,26 +839,82 @@ __global__ void cm_translate_kernel(int32_t n, int32_t n_seg, const int64_t *__r
         else
             hi = mid - 1;
     }
-    if (l - (int)seg[lo] >= state[lo].x)
-        return;
-    const int4 r = rec[permA[l]];
-    rec2[l] = make_int4(rec[r.x].w, rec[r.y].w, rec[r.z].w, -1);
+    return lo;
 }
 
-// The rest of the search for every segment, after cm_first_kernel and
-// cm_translate_kernel, as one loop with one labelling pass per iteration:
-// kProbe (the first component's pick, on the renamed copy), kRoot (the root
-// of the next component: its lowest unreached cell), kSearch (clear the
-// component's labels, relabel it from the pick of the best pass so far).
-// Every loop ends on a block-uniform condition: each component is labelled
-// in full before the next starts, and the search moves only while the
-// eccentricity, bounded by the segment size, strictly grows.
+// inv[ordA[l]] = l for the positions l of each segment's first component.
+__global__ void cm_invert_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict__ seg,
+                                 const int4 *__restrict__ state, const int32_t *__restrict__ ordA,
+                                 int32_t *__restrict__ inv)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n)
+        return;
+    const int sg = segment_of(l, n_seg, seg);
+    if (l - (int)seg[sg] >= state[sg].x)
+        return;
+    inv[ordA[l]] = l;
+}
+
+// rec2[l] = (positions of the three neighbours of the cell at position l, -1)
+// for the positions of each segment's first component.
+__global__ void cm_rename_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict__ seg,
+                                 const int4 *__restrict__ state, const int4 *__restrict__ rec,
+                                 const int32_t *__restrict__ ordA, const int32_t *__restrict__ inv,
+                                 int4 *__restrict__ rec2)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n)
+        return;
+    const int sg = segment_of(l, n_seg, seg);
+    if (l - (int)seg[sg] >= state[sg].x)
+        return;
+    const int4 r = rec[ordA[l]];
+    rec2[l] = make_int4(inv[r.x], inv[r.y], inv[r.z], -1);
+}
+
+// Grid (n_seg, 2).  Workgroup y = 0: the sweep from the first component's
+// pick on rec2; probe[s] = its eccentricity.  Workgroup y = 1: the labels of
+// the first component from the first sweep's levels into perm, when every
+// level fits in LDS (the finish kernel discards them if the search moves).
+__global__ __launch_bounds__(kCmThreads) void cm_probe_kernel(
+    int4 *__restrict__ rec2, const int64_t *__restrict__ seg, const int4 *__restrict__ state,
+    const int32_t *__restrict__ ordA, const int32_t *__restrict__ levA,
+    const int32_t *__restrict__ inv, int32_t *__restrict__ ordB, int32_t *__restrict__ perm,
+    int32_t *__restrict__ probe)
+{
+    __shared__ union {
+        BfsLds bfs;
+        LabelLds label;
+    } lds;
+    const int s0 = (int)seg[blockIdx.x], s1 = (int)seg[blockIdx.x + 1];
+    if (s0 >= s1)
+        return;
+    const int4 st = state[blockIdx.x];
+    if (blockIdx.y == 0) {
+        const BfsResult r = bfs_pass(rec2, inv[st.z], s0, ordB, nullptr, ordA, lds.bfs);
+        if (threadIdx.x == 0)
+            probe[blockIdx.x] = r.ecc;
+    } else if (st.w <= kLabelCap) {
+        label_levels(rec2, ordA, levA, s0, st.x, st.y, perm, lds.label);
+    }
+}
+
+// The rest of the search for every segment, after cm_probe_kernel, as one
+// loop with one full labelling pass (cm_pass, on the uploaded graph) per
+// iteration: kRoot (the root of the next component: its lowest cell not yet
+// labelled), kSearch (clear the component's labels, relabel it from the pick
+// of the best pass so far).  Every loop ends on a block-uniform condition:
+// each component is labelled in full before the next starts, and the search
+// moves only while the eccentricity, bounded by the segment size, strictly
+// grows.  Records of cells the first sweep reached carry its marks (not -1),
+// so they count as labelled when later roots are sought.
 __global__ __launch_bounds__(kCmThreads) void cm_finish_kernel(
-    int4 *__restrict__ rec, int4 *__restrict__ rec2, const int64_t *__restrict__ seg,
-    const int4 *__restrict__ state, int32_t *__restrict__ permA, int32_t *__restrict__ permB,
+    int4 *__restrict__ rec, const int64_t *__restrict__ seg, const int4 *__restrict__ state,
+    const int32_t *__restrict__ probe, int32_t *__restrict__ permA, int32_t *__restrict__ permB,
     int32_t *__restrict__ perm, int32_t *__restrict__ passes)
 {
-    enum { kProbe, kRoot, kSearch };
+    enum { kRoot, kSearch };
     __shared__ PassLds lds;
     const int tid = threadIdx.x;
     const int s0 = (int)seg[blockIdx.x], s1 = (int)seg[blockIdx.x + 1];
@@ -456,18 +925,30 @@ __global__ __launch_bounds__(kCmThreads) void cm_finish_kernel(
     rr.ecc = st.y;
     rr.pick = st.z;
     int32_t *best = permA, *trial = permB;
-    int npass = s0 < s1 ? 1 : 0;
+    int npass = s0 < s1 ? 2 : 0;  // the two sweeps of the fast route
     int next = s0;
     int scan_from = s0;
-    int mode = s0 < s1 ? kProbe : kRoot;
+    int mode = kRoot;
+    if (s0 < s1) {
+        if (probe[blockIdx.x] > rr.ecc) {
+            mode = kSearch;  // relabel exactly from the same pick
+        } else {
+            if (st.w > kLabelCap) {
+                // levels too wide for the LDS labelling: a full pass from the
+                // same root (the segment's lowest id) on cleared labels
+                for (int v = s0 + tid; v < s1; v += kCmThreads)
+                    rlabel[4 * v + 3] = -1;
+                __threadfence_block();
+                __syncthreads();
+                (void)cm_pass(rec, s0, s0, perm, lds);
+            }
+            next += rr.count;
+        }
+    }
     for (;;) {
-        int4 *graph = rec;
         int root;
         int32_t *out = trial;
-        if (mode == kProbe) {
-            graph = rec2;
-            root = rlabel[4 * rr.pick + 3];
-        } else if (mode == kRoot) {
+        if (mode == kRoot) {
             if (next >= s1)
                 break;
             root = s1;
@@ -498,7 +979,7 @@ __global__ __launch_bounds__(kCmThreads) void cm_finish_kernel(
             __syncthreads();
             root = rr.pick;
         }
-        const PassResult r = cm_pass(graph, root, next, out, lds);
+        const PassResult r = cm_pass(rec, root, next, out, lds);
         ++npass;
         if (mode == kRoot) {
             rr = r;
@@ -506,14 +987,10 @@ __global__ __launch_bounds__(kCmThreads) void cm_finish_kernel(
             continue;
         }
         if (r.ecc > rr.ecc) {
-            // a probe only reports the growth: the search then relabels
-            // exactly from the same pick
-            if (mode == kSearch) {
-                rr = r;
-                int32_t *t = best;
-                best = trial;
-                trial = t;
-            }
+            rr = r;
+            int32_t *t = best;
+            best = trial;
+            trial = t;
             mode = kSearch;
             continue;
         }
@@ -569,22 +1046,35 @@ hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *
     return hipGetLastError();
 }
 
-hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t n, int32_t n_seg,
-                              const int64_t *seg, int32_t *permA, int32_t *permB, int32_t *perm,
-                              int32_t *label, int32_t *passes, hipStream_t s)
+hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe, int32_t n,
+                              int32_t n_seg, const int64_t *seg, int32_t *permA, int32_t *permB,
+                              int32_t *levA, int32_t *perm, int32_t *label, int32_t *passes,
+                              hipStream_t s)
 {
     hipLaunchKernelGGL(cm_first_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, seg, permA,
-                       state);
+                       levA, state);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(cm_translate_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, n_seg, seg,
-                       state, rec, permA, rec2);
+    // label serves as the inverse of the first order until invert_kernel
+    // writes the final one
+    hipLaunchKernelGGL(cm_invert_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, n_seg, seg,
+                       state, permA, label);
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(cm_finish_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, rec2, seg,
-                       state, permA, permB, perm, passes);
+    hipLaunchKernelGGL(cm_rename_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, n_seg, seg,
+                       state, rec, permA, label, rec2);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(cm_probe_kernel, dim3(n_seg, 2), dim3(kCmThreads), 0, s, rec2, seg, state,
+                       permA, levA, label, permB, perm, probe);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(cm_finish_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, seg, state,
+                       probe, permA, permB, perm, passes);
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;

@@ -39,7 +39,12 @@ fv_status fail(fv_status code, const char *fmt, ...)
     } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr int64_t kMaxCells = (int64_t(1) << 31) - 4096;
+// Device code forms offsets such as 6 ld + i (normals) and 4 v + 3 (the
+// label field of a renumbering record) in 32-bit integers, and the labelling
+// packs a degree and a cell id into 32 bits: 8 ld < 2^31 keeps all of them
+// exact (about 77 GB of arena at this size).
+constexpr int64_t kMaxCells = (int64_t(1) << 28) - 4096;
+static_assert(kMaxCells == FV_MAX_CELLS, "FV_MAX_CELLS");
 constexpr int32_t kMaxSegments = 1 << 16;
 
 size_t align_up(size_t x)
@@ -65,13 +70,15 @@ struct Layout {
         nrm = align_up(ld * 6 * 8);
         area = align_up(ld * 8);
         idx = align_up(ld * 4);
-        // >= AoS normals (48 B), state (32 B), CM records, two orders and
-        // renamed records (40 B)
+        // >= AoS normals (48 B), state (32 B), renumbering scratch (records,
+        // two orders, renamed records, level starts: 44 B)
         scratch = align_up(ld * 48);
         // segment offsets (int64), per-segment dt (double), per-segment pass
-        // counts (int32), per-segment first-pass results (int4)
+        // counts (int32), per-segment first-sweep results (int4) and
+        // second-sweep eccentricities (int32, padded to 8 bytes)
         seg = align_up((size_t)(kMaxSegments + 1) * 8) + align_up((size_t)kMaxSegments * 8) +
-              align_up((size_t)kMaxSegments * 4) + align_up((size_t)kMaxSegments * 16);
+              align_up((size_t)kMaxSegments * 4) + align_up((size_t)kMaxSegments * 16) +
+              align_up((size_t)kMaxSegments * 8);
         corr = align_up(fvk::kCorrFragShorts * 2) + align_up(fvk::kCorrBias * 4) +
                align_up(fvk::kCorrAdjFragShorts * 2) +
                align_up((size_t)fvk::kCorrAdjMaxGrid * fvk::kCorrParams * 4);
@@ -109,7 +116,8 @@ struct fv_ctx {
     int64_t *seg_dev = nullptr;   // segment offsets (n_seg + 1)
     double *dt_dev = nullptr;     // per-segment dt of `coef`
     int32_t *passes_dev = nullptr;
-    int4 *cm_state = nullptr;     // per-segment first-pass results of the renumbering
+    int4 *cm_state = nullptr;     // per-segment first-sweep results of the renumbering
+    int32_t *cm_probe = nullptr;  // per-segment eccentricity of the second sweep
 
     int32_t n_seg = 1;
     std::vector<int64_t> seg_host;  // segment offsets; a segment is an independent mesh
@@ -133,6 +141,7 @@ struct fv_ctx {
     bool closed = false;  // every cell: n_2 == -(n_0 + n_1) exactly
     bool fixed = false;   // every n_0, n_1 component is k 2^-32, |k| < 2^31 (and `closed`)
     bool narrow = false;  // every neighbour offset of the working order fits in 16 bits
+    bool cm_passes = false;  // passes_dev holds the counts of a renumbering of this mesh
 };
 
 namespace {
@@ -246,8 +255,9 @@ fv_status regather_geometry(fv_ctx *c)
 
 // Cuthill-McKee labelling of every segment of the uploaded graph into
 // c->perm / c->label, one workgroup per segment, all on the device.
-// Scratch use (bytes per cell): records 16, two candidate orders 4 + 4,
-// renamed records 16 (ld is a multiple of 64, so every part stays aligned).
+// Scratch use (bytes per cell): records 16, two orders 4 + 4, renamed
+// records 16, level starts 4 (ld is a multiple of 64, so every part stays
+// aligned).
 fv_status cm_order(fv_ctx *c)
 {
     const int32_t n = c->n;
@@ -256,9 +266,11 @@ fv_status cm_order(fv_ctx *c)
     int32_t *permA = reinterpret_cast<int32_t *>(rec + ld);
     int32_t *permB = permA + ld;
     int4 *rec2 = reinterpret_cast<int4 *>(permB + ld);
+    int32_t *levA = reinterpret_cast<int32_t *>(rec2 + ld);
     HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
-    HIP_TRY(fvk::launch_cm_segments(rec, rec2, c->cm_state, n, c->n_seg, c->seg_dev, permA,
-                                    permB, c->perm, c->label, c->passes_dev, c->stream));
+    HIP_TRY(fvk::launch_cm_segments(rec, rec2, c->cm_state, c->cm_probe, n, c->n_seg, c->seg_dev,
+                                    permA, permB, levA, c->perm, c->label, c->passes_dev,
+                                    c->stream));
     return FV_OK;
 }
 
@@ -426,6 +438,8 @@ fv_status fv_create(int64_t n_cells, double gamma, void *d_arena, size_t arena_b
     p += align_up((size_t)kMaxSegments * 4);
     c->cm_state = reinterpret_cast<int4 *>(p);
     p += align_up((size_t)kMaxSegments * 16);
+    c->cm_probe = reinterpret_cast<int32_t *>(p);
+    p += align_up((size_t)kMaxSegments * 8);
     c->corr_frags = reinterpret_cast<short *>(p);
     p += align_up(fvk::kCorrFragShorts * 2);
     c->corr_bias = reinterpret_cast<float *>(p);
@@ -475,6 +489,7 @@ fv_status upload(fv_ctx *c, int32_t n_seg, const int64_t *seg, const int32_t *nb
     const size_t n = (size_t)c->n;
     c->mesh_ready = false;
     c->state_ready = false;
+    c->cm_passes = false;
     drop_graph(c);
     c->closed = normals_closed(c->n, nrm);
     c->fixed = c->closed && normals_fixed(c->n, nrm);
@@ -578,12 +593,14 @@ fv_status fv_renumber(fv_ctx *c, int32_t method, int32_t *perm_out)
     double4 *spare = c->U[c->cur ^ 1];
     if (c->state_ready)
         HIP_TRY(fvk::launch_gather_state(c->n, c->label, c->U[c->cur], spare, c->stream));
+    c->cm_passes = false;
     if (method == FV_ORDER_IDENTITY) {
         HIP_TRY(fvk::launch_iota(c->perm, c->n, c->stream));
         HIP_TRY(fvk::launch_iota(c->label, c->n, c->stream));
     } else {
         if (fv_status st = cm_order(c))
             return st;
+        c->cm_passes = true;
     }
     if (fv_status st = regather_geometry(c))
         return st;
@@ -725,6 +742,8 @@ fv_status fv_renumber_passes(fv_ctx *c, int32_t *passes)
         return fail(FV_EINVAL, "null passes array");
     if (!c->mesh_ready)
         return fail(FV_ESTATE, "upload the mesh first");
+    if (!c->cm_passes)
+        return fail(FV_ESTATE, "no Cuthill-McKee renumbering of this mesh yet");
     HIP_TRY(hipMemcpyAsync(passes, c->passes_dev, (size_t)c->n_seg * sizeof(int32_t),
                            hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));

@@ -25,6 +25,7 @@ FV_ENOMEM = -5
 FV_ORDER_IDENTITY = 0
 FV_ORDER_CM = 1
 FV_CORRECTION_PARAMS = 5252
+FV_MAX_CELLS = 268431360  # largest mesh a context accepts (device offsets are 32-bit)
 
 # every symbol include/fvgpu.h declares
 EXPORTS = (

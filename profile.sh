@@ -6,19 +6,19 @@
 # in the same run as the calibration, then L2 hits and misses of the step on
 # the random order and on the renumbered order.  Output: prof_* under
 # $FV_PROFILE_DIR (default: profile_out/ at the repository root).  Summarise
-# with: python -m paper_1408_5715_amd.profile_summary (same FV_PROFILE_DIR)
+# with: python profile_summary.py (same FV_PROFILE_DIR)
 #
 # `profile.sh learned`: the same three runs for the learned-correction
-# kernels (paper_1408_5715_amd/profile_learned.py: 20 corrected steps on the
+# kernels (profile_learned.py: 20 corrected steps on the
 # 1024 x 1024 mesh, 4 corrected adjoint steps on the 32-flow training batch),
 # with MFMA counters in place of the byte counters.  Output lprof_*.
 #
 # `profile.sh renumber`: two counter passes (wave and instruction counters;
 # texture-addresser, L1-to-L2 and clock counters) over one bench.py job of
 # the 2,097,152-cell workload, for the renumbering kernels and the step.
-# Output rprof_*.  Summarise with profile_summary.py renumber.
+# Output rprof_*.  Summarise with python profile_summary.py renumber.
 set -euo pipefail
-ROOT="$(cd "$(dirname "$0")/.." && pwd)"
+ROOT="$(cd "$(dirname "$0")" && pwd)"
 OUT="${FV_PROFILE_DIR:-$ROOT/profile_out}"
 mkdir -p "$OUT"
 export TMPDIR=/tmp
@@ -26,7 +26,7 @@ export PYTHONPATH="$ROOT${PYTHONPATH:+:$PYTHONPATH}"
 cd /tmp
 if [ "${1:-}" = "renumber" ]; then
     # one job of bench.py (renumbering + 20 steps) under two counter passes
-    JOB=(python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random)
+    JOB=(python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random --hbm-N 0)
     echo "[profile] renumber: SQ counters" >&2
     timeout -s KILL 120 rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY \
         SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_INSTS_VALU SQ_INSTS_VMEM_RD -f csv \
@@ -41,31 +41,31 @@ fi
 if [ "${1:-}" = "learned" ]; then
     echo "[profile] learned: kernel trace" >&2
     timeout -k 10 300 rocprofv3 --kernel-trace --stats -f csv -d "$OUT/lprof_trace" -o trace -- \
-        python3 -m paper_1408_5715_amd.profile_learned --adjoint > "$OUT/lprof_trace.log" 2>&1
+        python3 "$ROOT/profile_learned.py" --adjoint > "$OUT/lprof_trace.log" 2>&1
     echo "[profile] learned: MFMA counters" >&2
     timeout -s KILL 120 rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_MFMA SQ_INSTS_VALU_MFMA_MOPS_BF16 \
         SQ_VALU_MFMA_BUSY_CYCLES SQ_WAVES SQ_INSTS_LDS GRBM_GUI_ACTIVE -f csv -d "$OUT/lprof_mfma" \
-        -o mfma -- python3 -m paper_1408_5715_amd.profile_learned --adjoint > "$OUT/lprof_mfma.log" 2>&1
+        -o mfma -- python3 "$ROOT/profile_learned.py" --adjoint > "$OUT/lprof_mfma.log" 2>&1
     echo "[profile] learned: byte counters" >&2
     timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -f csv -d "$OUT/lprof_fetch" -o fetch -- \
-        python3 -m paper_1408_5715_amd.profile_learned --probe-copy > "$OUT/lprof_fetch.log" 2>&1
+        python3 "$ROOT/profile_learned.py" --probe-copy > "$OUT/lprof_fetch.log" 2>&1
     echo "[profile] done" >&2
     exit 0
 fi
 echo "[profile] kernel trace" >&2
 timeout -k 10 300 rocprofv3 --kernel-trace --stats -f csv -d "$OUT/prof_trace" -o trace -- \
-    python3 "$ROOT/bench.py" --steps 3 --warmup 1 --no-cpu-baseline --skip-random \
+    python3 "$ROOT/bench.py" --steps 3 --warmup 1 --no-cpu-baseline --skip-random --hbm-N 0 \
     > "$OUT/prof_trace.log" 2>&1
 echo "[profile] FETCH_SIZE" >&2
 timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -f csv -d "$OUT/prof_fetch" -o fetch -- \
-    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random \
+    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random --hbm-N 0 \
     --probe-copy > "$OUT/prof_fetch.log" 2>&1
 echo "[profile] WRITE_SIZE" >&2
 timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -f csv -d "$OUT/prof_write" -o write -- \
-    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random \
+    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random --hbm-N 0 \
     --probe-copy > "$OUT/prof_write.log" 2>&1
 echo "[profile] L2 hits and misses (random order, then renumbered)" >&2
 timeout -s KILL 120 rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d "$OUT/prof_l2" -o l2 -- \
-    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline \
+    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --hbm-N 0 \
     > "$OUT/prof_l2.log" 2>&1
 echo "[profile] done" >&2

@@ -35,6 +35,11 @@ def test_arena_bytes():
     assert fv.fv_arena_bytes(0) == 0
     assert fv.fv_arena_bytes(-5) == 0
     assert fv.fv_arena_bytes(1 << 31) == 0
+    # device offsets such as 6 ld + i are 32-bit: the bound keeps 8 ld < 2^31
+    assert fv.FV_MAX_CELLS == (1 << 28) - 4096
+    assert fv.fv_arena_bytes(fv.FV_MAX_CELLS) > 0
+    assert fv.fv_arena_bytes(fv.FV_MAX_CELLS + 1) == 0
+    assert fv.fv_arena_bytes((1 << 31) - 4096) == 0
     b = fv.fv_arena_bytes(8192)
     # fixed parts: the per-mesh tables of a batch (up to 65536 meshes, 2.4 MB)
     # and the correction's weights and per-workgroup gradients (512 x 5252 floats)
@@ -59,6 +64,8 @@ def test_create_rejects_bad_arguments():
         (n, 1.4, 0, nb),
         (n, 1.4, FAKE_ARENA + 8, nb),
         (n, 1.4, FAKE_ARENA, nb - 1),
+        (fv.FV_MAX_CELLS + 1, 1.4, FAKE_ARENA, 1 << 40),
+        (1 << 30, 1.4, FAKE_ARENA, 1 << 40),
     ]
     for args in cases:
         with pytest.raises(fv.FVError) as e:

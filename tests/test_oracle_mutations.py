@@ -38,8 +38,9 @@ MUTATIONS = {
     "S_BW from prefix minimum": ("if (s[i + 1] < s[i])\n            s[i] = s[i + 1];",
                                  "if (s[i + 1] > s[i])\n            s[i] = s[i + 1];"),
     "bandwidth not doubled": ("out[1] = 2 * B + 1;", "out[1] = B + 1;"),
-    "AM1 ties move the candidate": ("if (local_max > global_max) {", "if (local_max >= global_max) {"),
-    "AM1 scans from node(I) too": ("if (p < 0 || knb[g] == vI)", "if (p < 0)"),
+    "AM1 ties go to the larger id": ("(score == best_score && k < best)",
+                                     "(score == best_score && k > best)"),
+    "AM1 scores node(I) too": ("if (p >= 0 && knb[g] != vI)", "if (p >= 0)"),
     "bounded pattern ignores its stop rule": ("if (max_imp > bound && I > 0)",
                                               "if (max_imp > bound + 1000000 && I > 0)"),
     "bounded pattern executes node(I) too": ("const int run = k < I && !ghost[k];",

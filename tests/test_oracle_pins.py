@@ -103,6 +103,19 @@ def test_step_composes(o):
     assert np.array_equal(b, o.step(m.nbr, m.nrm, m.area, U0, dt, 12))
 
 
+def test_threaded_steps_equal_sequential(o):
+    """The all-core timing variant shares the cells of each step among
+    threads; every update reads only the previous state, so it is bitwise the
+    sequential oracle."""
+    m, U0, dt = pins.c1_like(16)
+    ref = o.step(m.nbr, m.nrm, m.area, U0, dt, 9)
+    got, used = o.step_threads(m.nbr, m.nrm, m.area, U0, dt, 9, 4)
+    assert 1 <= used <= 4
+    assert np.array_equal(got, ref)
+    with pytest.raises(RuntimeError):
+        o.step_threads(m.nbr, m.nrm, m.area, U0, dt, 1, 0)
+
+
 def test_bad_arguments(o):
     m, U0, dt = pins.c1_like(4)
     with pytest.raises(RuntimeError):
