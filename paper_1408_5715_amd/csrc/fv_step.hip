@@ -150,6 +150,13 @@ __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__
         nxs[2] = nrm[4 * ld + i];
         nys[2] = nrm[5 * ld + i];
     }
+    // The normals enter the flux as opaque values, so every layout runs the
+    // same arithmetic: otherwise the compiler folds the derived normal's
+    // negation into the products of face 2 and fuses different pairs into
+    // FMAs than with a loaded normal, which changes the rounding.
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+        asm volatile("" : "+v"(nxs[f]), "+v"(nys[f]));
 
     const double4 Ui = U[i];
     const Prim L = primitives(Ui, gamma);
