@@ -288,6 +288,38 @@ int64_t fv_bytes_per_update(const fv_ctx *ctx);
  */
 fv_status fv_check_state(fv_ctx *ctx);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): fv_step
+ * on a mesh and state that already live in device memory, with no context
+ * and no arena.  The step's scratch (the second state buffer of the
+ * ping-pong and dt / V_T per cell, 40 bytes per cell) is a static device
+ * array of FV_STATIC_MAX_CELLS cells that each device the library runs on
+ * holds until the process ends.  Calls on one device share that array and
+ * leave their values in it (each call writes it before reading it), so calls
+ * that overlap on one device race: issue them on one stream, or serialise
+ * them.
+ *   n_cells  1 .. FV_STATIC_MAX_CELLS; FV_EINVAL beyond (nothing is
+ *            allocated instead).
+ *   d_nbr    device int32 [3][n_cells] (structure of arrays: neighbour
+ *            across face f of cell i at d_nbr[f * n_cells + i]); every index
+ *            in [0, n_cells) and the mesh closed as fv_upload_mesh requires
+ *            (not checked: the arrays stay on the device).
+ *   d_nrm    device double [6][n_cells]: nx_0, ny_0, nx_1, ny_1, nx_2, ny_2
+ *            (outward, scaled by the face length), structure of arrays.
+ *   d_area   device double [n_cells], > 0.
+ *   d_U      device double [n_cells][4] (rho, rho u, rho v, E), 32-byte
+ *            aligned, in/out: advanced by n_steps steps of size dt.
+ *   gamma    finite and > 1.
+ * The result is bitwise that of fv_step on the same mesh and state.  The
+ * device is the current one; asynchronous on hip_stream (NULL: the null
+ * stream).  Calls no allocating routine.
+ */
+#define FV_STATIC_MAX_CELLS 1048576
+fv_status fv_step_static(int64_t n_cells, const int32_t *d_nbr, const double *d_nrm,
+                         const double *d_area, double *d_U, int32_t n_steps, double dt,
+                         double gamma, void *hip_stream);
+
 /* Release the host-side context.  Does not touch the arena. */
 fv_status fv_destroy(fv_ctx *ctx);
 

@@ -14,6 +14,7 @@ from .fvgpu import (  # noqa: F401
     FV_OK,
     FV_CORRECTION_PARAMS,
     FV_MAX_CELLS,
+    FV_STATIC_MAX_CELLS,
     FV_ORDER_CM,
     FV_ORDER_IDENTITY,
     FVError,
@@ -32,6 +33,7 @@ from .fvgpu import (  # noqa: F401
     fv_set_launch,
     fv_step_adjoint,
     fv_step_batch,
+    fv_step_static,
     fv_upload_batch,
     fv_step,
     fv_upload_mesh,

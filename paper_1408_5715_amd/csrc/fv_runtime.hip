@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -841,6 +842,120 @@ fv_status fv_destroy(fv_ctx *c)
 const char *fv_last_error(void)
 {
     return g_last_error.c_str();
+}
+
+}  // extern "C"
+
+// ---- fv_step_static: the step with its scratch in a static device array ----
+//
+// For callers that cannot allocate device memory (code under HIP graph
+// capture, serving loops): the second state buffer of the ping-pong and the
+// per-cell dt / V_T live in `scratch`, a file-scope device array of
+// kStaticMaxCells cells that every device running the library holds until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: its device address comes from hipGetSymbolAddress, once
+// per device, and only that address is passed to kernels.
+
+namespace {
+
+constexpr int64_t kStaticMaxCells = FV_STATIC_MAX_CELLS;
+constexpr int kStaticMaxDevices = 64;
+// per cell: the other state buffer (32 B), then dt / V_T (8 B)
+constexpr size_t kStaticStateBytes = (size_t)kStaticMaxCells * 32;
+constexpr size_t kStaticBytes = kStaticStateBytes + (size_t)kStaticMaxCells * 8;
+
+__device__ __align__(256) char scratch[kStaticBytes];
+
+std::mutex g_static_mu;
+void *g_static_ptr[kStaticMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+fv_status static_scratch(char **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kStaticMaxDevices)
+        return fail(FV_EHIP, "device %d outside the %d devices fv_step_static serves", dev,
+                    kStaticMaxDevices);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr)
+            return fail(FV_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_static_ptr[dev] = ptr;
+    }
+    *out = static_cast<char *>(g_static_ptr[dev]);
+    return FV_OK;
+}
+
+// coef[i] = dt * (1 / area[i]): the same two roundings as the context path
+// (1 / V_T formed at upload, times dt when dt changes).
+__global__ void static_coef_kernel(int32_t n, const double *__restrict__ area, double dt,
+                                   double *__restrict__ coef)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        coef[i] = dt * (1.0 / area[i]);
+}
+
+__global__ void static_copy_kernel(int32_t n, const double4 *__restrict__ src,
+                                   double4 *__restrict__ dst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        dst[i] = src[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+fv_status fv_step_static(int64_t n_cells, const int32_t *d_nbr, const double *d_nrm,
+                         const double *d_area, double *d_U, int32_t n_steps, double dt,
+                         double gamma, void *hip_stream)
+{
+    g_last_error.clear();
+    if (n_cells <= 0 || n_cells > kStaticMaxCells)
+        return fail(FV_EINVAL, "n_cells %lld outside [1, %lld] (the static scratch array's size)",
+                    (long long)n_cells, (long long)kStaticMaxCells);
+    if (!d_nbr || !d_nrm || !d_area || !d_U)
+        return fail(FV_EINVAL, "null device array");
+    if (reinterpret_cast<uintptr_t>(d_U) % 32 != 0 || reinterpret_cast<uintptr_t>(d_nrm) % 8 != 0 ||
+        reinterpret_cast<uintptr_t>(d_area) % 8 != 0 || reinterpret_cast<uintptr_t>(d_nbr) % 4 != 0)
+        return fail(FV_EINVAL, "misaligned device array (d_U needs 32 bytes)");
+    if (n_steps < 0)
+        return fail(FV_EINVAL, "n_steps %d < 0", n_steps);
+    if (!(std::isfinite(dt) && dt > 0.0))
+        return fail(FV_EINVAL, "dt %g must be finite and > 0", dt);
+    if (!(std::isfinite(gamma) && gamma > 1.0))
+        return fail(FV_EINVAL, "gamma %g must be finite and > 1", gamma);
+    if (n_steps == 0)
+        return FV_OK;
+    char *base = nullptr;
+    if (fv_status st = static_scratch(&base))
+        return st;
+    const int32_t n = (int32_t)n_cells;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    double4 *other = reinterpret_cast<double4 *>(base);
+    double *coef = reinterpret_cast<double *>(base + kStaticStateBytes);
+    double4 *buf[2] = {reinterpret_cast<double4 *>(d_U), other};
+    hipLaunchKernelGGL(static_coef_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, d_area, dt,
+                       coef);
+    HIP_TRY(hipGetLastError());
+    int cur = 0;
+    for (int32_t k = 0; k < n_steps; ++k) {
+        HIP_TRY(fvk::launch_step(n, n, buf[cur], buf[cur ^ 1], d_nbr, nullptr, d_nrm, nullptr,
+                                 coef, gamma, false, false, false, 256, 0, s));
+        cur ^= 1;
+    }
+    if (cur == 1) {
+        hipLaunchKernelGGL(static_copy_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, other,
+                           buf[0]);
+        HIP_TRY(hipGetLastError());
+    }
+    return FV_OK;
 }
 
 }  // extern "C"

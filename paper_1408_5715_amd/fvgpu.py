@@ -26,6 +26,7 @@ FV_ORDER_IDENTITY = 0
 FV_ORDER_CM = 1
 FV_CORRECTION_PARAMS = 5252
 FV_MAX_CELLS = 268431360  # largest mesh a context accepts (device offsets are 32-bit)
+FV_STATIC_MAX_CELLS = 1048576  # largest mesh fv_step_static takes (its static scratch array)
 
 # every symbol include/fvgpu.h declares
 EXPORTS = (
@@ -33,7 +34,7 @@ EXPORTS = (
     "fv_upload_state_device", "fv_renumber", "fv_step", "fv_step_batch", "fv_step_adjoint",
     "fv_step_adjoint_grad", "fv_set_correction", "fv_restrict", "fv_set_launch",
     "fv_renumber_passes", "fv_download_state", "fv_download_state_device", "fv_bytes_per_update",
-    "fv_check_state", "fv_destroy", "fv_last_error",
+    "fv_check_state", "fv_destroy", "fv_last_error", "fv_step_static",
 )
 
 
@@ -66,6 +67,7 @@ def lib() -> ctypes.CDLL:
         L.fv_step_adjoint.argtypes = [vp, vp, vp, dbl]
         L.fv_step_adjoint_grad.argtypes = [vp, vp, vp, dbl, vp]
         L.fv_restrict.argtypes = [vp, i64, vp, vp, i64, i32, vp, vp]
+        L.fv_step_static.argtypes = [i64, vp, vp, vp, vp, i32, dbl, dbl, vp]
         L.fv_set_correction.argtypes = [vp, vp, i32]
         L.fv_renumber_passes.argtypes = [vp, vp]
         L.fv_upload_state.argtypes = [vp, vp]
@@ -153,6 +155,17 @@ def fv_restrict(d_src, d_idx, d_w, d_out, stream=None) -> None:
     n, k = d_idx.shape
     _check(lib().fv_restrict(_ptr(d_src), int(d_src.shape[0]), _ptr(d_idx), _ptr(d_w), int(n),
                              int(k), _ptr(d_out), None if stream is None else stream.cuda_stream))
+
+
+def fv_step_static(d_nbr, d_nrm, d_area, d_U, n_steps: int, dt: float, gamma: float = 1.4,
+                   stream=None) -> None:
+    """fv_step without a context or arena (no allocation): device tensors
+    nbr int32 [3, n], nrm float64 [6, n], area float64 [n], U float64 [n, 4]
+    (advanced in place), scratch in the library's static device array."""
+    n = int(d_U.shape[0])
+    _check(lib().fv_step_static(n, _ptr(d_nbr), _ptr(d_nrm), _ptr(d_area), _ptr(d_U),
+                                int(n_steps), float(dt), float(gamma),
+                                None if stream is None else stream.cuda_stream))
 
 
 def fv_set_correction(ctx: int, params) -> None:
