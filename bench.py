@@ -90,11 +90,20 @@ def cpu_threads() -> int:
 
 
 def cpu_model() -> str:
+    """The host CPU's model name with its family, model and stepping numbers
+    (some hosts report only a short model name)."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
-            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+            for ln in f:
+                if ":" in ln:
+                    k, v = (x.strip() for x in ln.split(":", 1))
+                    fields.setdefault(k, v)
     except OSError:
         return ""
+    name = fields.get("model name", "")
+    ids = [f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping") if k in fields]
+    return f"{name} ({', '.join(ids)})" if ids else name
 
 
 def cpu_baseline(m, U0, dt, fv_steps: int, sample_steps: int) -> dict:
