@@ -4,13 +4,15 @@ and the autograd rollout, against the CPU reference (autograd through
 oracle/learned_ref.py with bfloat16 rounding differentiated as the identity,
 the rule the kernel implements).
 
-Bar: the kernel rounds the backward quantities (output cotangents, the
-pre-activation cotangents) to bfloat16 for the MFMA products and sums in
-float32 in another order than the reference, so each product carries a
-relative error up to about 2^-8; the correction's part of the state
-cotangent and the parameter gradient (sums of many such products) must
-agree to 3 % of their size.  The plain part of the adjoint is unchanged and
-exact (tests/test_gpu_adjoint.py)."""
+Bar: the kernel rounds the output and pre-activation cotangents to bfloat16
+before the MFMA products (relative error at most 2^-9 each, so at most
+2^-8 on a product of two rounded factors) and sums in float32 in another
+order than the reference.  An entry of the correction's part of the state
+cotangent, or of the parameter gradient, is a sum of such products, so it
+carries at most 2^-8 of the sum of its terms' magnitudes; terms of mixed
+sign can cancel, so the bar is twice that against the largest entry,
+2 * 2^-8 ~ 7.8e-3 (measured 0.9-3.6e-3).  The plain part of the adjoint is
+unchanged and exact (tests/test_gpu_adjoint.py)."""
 
 import numpy as np
 import pytest
@@ -22,7 +24,7 @@ from oracle import learned_ref, torch_ref
 
 pytestmark = pytest.mark.gpu
 
-TOL = 3e-2
+TOL = 2 * 2.0**-8
 
 
 @pytest.fixture(scope="module")
