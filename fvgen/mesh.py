@@ -179,3 +179,175 @@ def shuffled_periodic_mesh(N: int, L: float = 10.0, jitter: float = 0.2, mesh_se
     """The workload mesh: jittered periodic mesh with cells randomly permuted."""
     m = periodic_mesh(N, L, jitter, mesh_seed)
     return permute_mesh(m, random_permutation(m.n, perm_seed))
+
+
+def irregular_periodic_mesh(N: int, L: float = 10.0, jitter: float = 0.2, seed: int = 1,
+                            flip_fraction: float = 0.35, passes: int = 3,
+                            refine: tuple | None = None) -> Mesh:
+    """A doubly periodic triangle mesh of irregular topology (2 N^2 cells):
+    the jittered, snapped vertex grid of periodic_mesh, each quad split along
+    a random diagonal, then random edge flips (passes x flip_fraction of the
+    candidate edges per pass) between triangles that do not touch the
+    periodic seam, each flip kept only if the two new triangles have area
+    at least 0.05 h^2.  Vertex degrees then range over 3-10 and breadth-first
+    levels lose the grid's regularity, as on unstructured (Delaunay-type)
+    meshes.  Conventions as for periodic_mesh: counter-clockwise vertices,
+    face f = edge P_f -> P_{f+1}, normal (dy, -dx); snapped coordinates, so
+    a face's normal is the exact negative of its twin's and a cell's normals
+    sum to exactly zero.  Cells in construction order (permute them with
+    random_permutation for a random order).
+
+    refine = (cx, cy, radius, levels): local refinement, like a mesh graded
+    towards a point: `levels` times, every triangle whose centroid lies
+    within `radius` of (cx, cy) (no periodic wrap) is split into three at its
+    snapped centroid (its outer edges are kept, so its neighbours are
+    untouched), followed by Delaunay edge flips (an edge flips when the
+    opposite vertex of one triangle lies inside the other's circumcircle)
+    among triangles away from the seam."""
+    if N < 4:
+        raise ValueError("N must be >= 4")
+    h = L / N
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = np.add.outer(np.arange(N) * h, np.zeros(N))
+    Y = np.add.outer(np.zeros(N), np.arange(N) * h)
+    if jitter > 0.0:
+        X[1:, 1:] += rng.uniform(-jitter * h, jitter * h, size=(N - 1, N - 1))
+        Y[1:, 1:] += rng.uniform(-jitter * h, jitter * h, size=(N - 1, N - 1))
+    X = _snap(X)
+    Y = _snap(Y)
+    Ls = float(L)
+
+    # corners as (vertex id, periodic shift x, periodic shift y); vid = i * N + j
+    def corner(i, j):
+        return ((i % N) * N + (j % N), int(i >= N), int(j >= N))
+
+    tris = []
+    diag = rng.integers(0, 2, size=(N, N))
+    for i in range(N):
+        for j in range(N):
+            a, b, c, d = corner(i, j), corner(i + 1, j), corner(i + 1, j + 1), corner(i, j + 1)
+            if diag[i, j] == 0:
+                tris += [[a, b, c], [a, c, d]]
+            else:
+                tris += [[a, b, d], [b, c, d]]
+
+    def xy(cn):
+        v, sx, sy = cn
+        return X.flat[v] + Ls * sx, Y.flat[v] + Ls * sy
+
+    def area2(t):
+        (x0, y0), (x1, y1), (x2, y2) = (xy(c) for c in t)
+        return (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0)
+
+    min_area2 = 2 * 0.05 * h * h
+    for _ in range(passes):
+        # interior edges: both triangles unshifted (away from the seam)
+        owner = {}
+        for t, tri in enumerate(tris):
+            if any(c[1] or c[2] for c in tri):
+                continue
+            for f in range(3):
+                owner[(tri[f][0], tri[(f + 1) % 3][0])] = (t, f)
+        edges = [e for e in owner if e[0] < e[1] and (e[1], e[0]) in owner]
+        rng.shuffle(edges)
+        busy = set()
+        for e in edges[: int(flip_fraction * len(edges))]:
+            t1, f1 = owner[e]
+            t2, f2 = owner[(e[1], e[0])]
+            if t1 in busy or t2 in busy:
+                continue
+            A, B = tris[t1][f1], tris[t1][(f1 + 1) % 3]
+            C = tris[t1][(f1 + 2) % 3]  # t1 = (A, B, C)
+            D = tris[t2][(f2 + 2) % 3]  # t2 = (B, A, D)
+            n1, n2 = [C, A, D], [D, B, C]
+            if area2(n1) < min_area2 or area2(n2) < min_area2:
+                continue
+            tris[t1], tris[t2] = n1, n2
+            busy.update((t1, t2))
+
+    if refine is not None:
+        cx, cy, radius, levels = refine
+        extra_x, extra_y = [], []  # coordinates of inserted vertices (ids N*N + k)
+
+        def xy(cn):  # noqa: F811 - also knows the inserted vertices
+            v, sx, sy = cn
+            if v < N * N:
+                return X.flat[v] + Ls * sx, Y.flat[v] + Ls * sy
+            return extra_x[v - N * N] + Ls * sx, extra_y[v - N * N] + Ls * sy
+
+        def incircle(a, b, c, d):
+            # > 0 when d lies inside the circumcircle of the counter-clockwise a, b, c
+            (ax, ay), (bx, by), (cx_, cy_), (dx, dy) = (xy(q) for q in (a, b, c, d))
+            m = np.array([[ax - dx, ay - dy, (ax - dx) ** 2 + (ay - dy) ** 2],
+                          [bx - dx, by - dy, (bx - dx) ** 2 + (by - dy) ** 2],
+                          [cx_ - dx, cy_ - dy, (cx_ - dx) ** 2 + (cy_ - dy) ** 2]])
+            return float(np.linalg.det(m))
+
+        for _ in range(levels):
+            out = []
+            for tri in tris:
+                pts = [xy(c) for c in tri]
+                gx = sum(p[0] for p in pts) / 3.0
+                gy = sum(p[1] for p in pts) / 3.0
+                if (gx - cx) ** 2 + (gy - cy) ** 2 > radius * radius:
+                    out.append(tri)
+                    continue
+                extra_x.append(float(_snap(np.array(gx))))
+                extra_y.append(float(_snap(np.array(gy))))
+                g = (N * N + len(extra_x) - 1, 0, 0)
+                a, b, c = tri
+                out += [[a, b, g], [b, c, g], [c, a, g]]
+            tris = out
+            for _ in range(4):  # Delaunay flips among unshifted triangles
+                owner = {}
+                for t, tri in enumerate(tris):
+                    if any(c[1] or c[2] for c in tri):
+                        continue
+                    for f in range(3):
+                        owner[(tri[f][0], tri[(f + 1) % 3][0])] = (t, f)
+                busy, flipped = set(), 0
+                for e in [e for e in owner if e[0] < e[1] and (e[1], e[0]) in owner]:
+                    t1, f1 = owner[e]
+                    t2, f2 = owner[(e[1], e[0])]
+                    if t1 in busy or t2 in busy:
+                        continue
+                    A, B, C = tris[t1][f1], tris[t1][(f1 + 1) % 3], tris[t1][(f1 + 2) % 3]
+                    D = tris[t2][(f2 + 2) % 3]
+                    if incircle(A, B, C, D) <= 0:
+                        continue
+                    n1, n2 = [C, A, D], [D, B, C]
+                    if area2(n1) <= 0 or area2(n2) <= 0:
+                        continue
+                    tris[t1], tris[t2] = n1, n2
+                    busy.update((t1, t2))
+                    flipped += 1
+                if not flipped:
+                    break
+
+    n = len(tris)
+    verts = np.empty((n, 3, 2), dtype=np.float64)
+    for t, tri in enumerate(tris):
+        for f, cn in enumerate(tri):
+            verts[t, f] = xy(cn)
+    x, y = verts[:, :, 0], verts[:, :, 1]
+    xn, yn = np.roll(x, -1, axis=1), np.roll(y, -1, axis=1)
+    nrm = np.empty((n, 3, 2), dtype=np.float64)
+    nrm[:, :, 0] = yn - y
+    nrm[:, :, 1] = -(xn - x)
+    area = 0.5 * ((x[:, 1] - x[:, 0]) * (y[:, 2] - y[:, 0]) - (x[:, 2] - x[:, 0]) * (y[:, 1] - y[:, 0]))
+    if np.any(area <= 0):
+        raise RuntimeError("non-positive triangle area")
+    perimeter = np.sqrt(nrm[:, :, 0] ** 2 + nrm[:, :, 1] ** 2).sum(axis=1)
+    centroid = np.stack([x.mean(axis=1) % Ls, y.mean(axis=1) % Ls], axis=1)
+    # neighbours: face (P_f -> P_f+1) meets the face (P_f+1 -> P_f) with the
+    # opposite relative periodic shift
+    face = {}
+    for t, tri in enumerate(tris):
+        for f in range(3):
+            a, b = tri[f], tri[(f + 1) % 3]
+            face[(a[0], b[0], b[1] - a[1], b[2] - a[2])] = (t, f)
+    nbr = np.empty((n, 3), dtype=np.int32)
+    for (va, vb, dx, dy), (t, f) in face.items():
+        nbr[t, f] = face[(vb, va, -dx, -dy)][0]
+    return Mesh(N=N, L=Ls, nbr=nbr, nrm=nrm, area=area, centroid=centroid, perimeter=perimeter,
+                ijk=np.full((n, 3), -1, dtype=np.int32), verts=verts)

@@ -38,6 +38,8 @@ class Oracle:
         L.oracle_cm_order.restype = ctypes.c_int
         L.oracle_am1_order.argtypes = [i64, vp, vp]
         L.oracle_am1_order.restype = ctypes.c_int
+        L.oracle_am1_exact_sbw.argtypes = [i64, vp, vp, vp]
+        L.oracle_am1_exact_sbw.restype = ctypes.c_int
         L.oracle_bandwidth.argtypes = [i64, vp, vp, vp]
         L.oracle_am1_bounded.argtypes = [i64, vp, i64, vp, vp, i64, vp, i64, vp, vp]
         L.oracle_am1_bounded.restype = ctypes.c_int
@@ -100,6 +102,17 @@ class Oracle:
         if self.lib.oracle_cm_order(nbr.shape[0], _p(nbr), _p(perm)) != 0:
             raise RuntimeError("oracle_cm_order failed")
         return perm
+
+    def am1_exact_sbw(self, nbr):
+        """(AM1 order, per-position serial bandwidth by Eq. exact-sbw; -1 where
+        undefined)."""
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        n = nbr.shape[0]
+        perm = np.empty(n, dtype=np.int32)
+        ex = np.empty(n, dtype=np.int64)
+        if self.lib.oracle_am1_exact_sbw(n, _p(nbr), _p(perm), _p(ex)) != 0:
+            raise RuntimeError("oracle_am1_exact_sbw failed")
+        return perm, ex
 
     def am1_order(self, nbr) -> np.ndarray:
         """Amoeba1 permutation (section 4.2), new label -> old id."""
@@ -173,6 +186,10 @@ def cm_order(*a, **k):
 
 def am1_order(*a, **k):
     return default().am1_order(*a, **k)
+
+
+def am1_exact_sbw(*a, **k):
+    return default().am1_exact_sbw(*a, **k)
 
 
 def bandwidth(*a, **k):

@@ -483,7 +483,7 @@ static int64_t am1_candidate(const int32_t *nbr, int64_t vI, const int64_t *pos,
  * root (section 4.2.2's pseudo-diameter endpoint).
  * Returns 0, or -1 on a bad argument or allocation failure.
  */
-int oracle_am1_order(int64_t n, const int32_t *nbr, int32_t *perm_out)
+static int am1_run(int64_t n, const int32_t *nbr, int32_t *perm_out, int64_t *exact_out)
 {
     if (n <= 0 || !nbr || !perm_out)
         return -1;
@@ -493,18 +493,23 @@ int oracle_am1_order(int64_t n, const int32_t *nbr, int32_t *perm_out)
     int64_t *uc = (int64_t *)malloc((size_t)n * sizeof(int64_t));    /* |u()| by position */
     int64_t *queue = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     int64_t *dist = (int64_t *)malloc((size_t)n * sizeof(int64_t));
-    if (!mark || !pos || !sv || !uc || !queue || !dist) {
+    int64_t *seen = (int64_t *)malloc((size_t)n * sizeof(int64_t)); /* union stamps */
+    if (!mark || !pos || !sv || !uc || !queue || !dist || !seen) {
         free(mark);
         free(pos);
         free(sv);
         free(uc);
         free(queue);
         free(dist);
+        free(seen);
         return -1;
     }
     for (int64_t v = 0; v < n; ++v) {
         pos[v] = -1;
         dist[v] = -1;
+        seen[v] = -1;
+        if (exact_out)
+            exact_out[v] = -1;
     }
     int64_t size = 0; /* nodes labelled so far, over all parts */
     int64_t scan = 0;
@@ -540,6 +545,23 @@ int oracle_am1_order(int64_t n, const int32_t *nbr, int32_t *perm_out)
             uc[m] = free_count;
             while (I < size && uc[I] == 0)
                 ++I;
+            if (exact_out && I <= m) {
+                /* Eq. exact-sbw for the node just added (i = m, part size
+                 * size = m + 1): (size - 1 - i) + |union of u(k), I <= k <= i|
+                 * + s(i).  The union is gathered from the stored neighbour
+                 * lists of positions I..i (vertices not yet in the part). */
+                int64_t un = 0;
+                for (int64_t k = I; k <= m; ++k) {
+                    int32_t kn[3];
+                    const int kd = distinct_neighbours(nbr, perm_out[k], kn);
+                    for (int g = 0; g < kd; ++g)
+                        if (pos[kn[g]] < 0 && seen[kn[g]] != m) {
+                            seen[kn[g]] = m;
+                            ++un;
+                        }
+                }
+                exact_out[m] = (size - 1 - m) + un + sv[m];
+            }
             if (I >= size)
                 break; /* component complete */
 
@@ -553,7 +575,29 @@ int oracle_am1_order(int64_t n, const int32_t *nbr, int32_t *perm_out)
     free(uc);
     free(queue);
     free(dist);
+    free(seen);
     return 0;
+}
+
+int oracle_am1_order(int64_t n, const int32_t *nbr, int32_t *perm_out)
+{
+    return am1_run(n, nbr, perm_out, NULL);
+}
+
+/*
+ * The serial bandwidth of each node of AM1's labelling by Eq. exact-sbw of
+ * section 4.3.1: exact_out[i] = (n - i) + |union of u(k) over I <= k <= i| +
+ * s(i), evaluated when node(i) joins the part (n = i + 1 then; the value
+ * does not change at later steps while I <= i, since every step takes a
+ * node of u(I) into the part), or -1 where I > i already then.  perm_out
+ * receives the AM1 order.  Returns 0, or -1 on a bad argument or
+ * allocation failure.
+ */
+int oracle_am1_exact_sbw(int64_t n, const int32_t *nbr, int32_t *perm_out, int64_t *exact_out)
+{
+    if (!exact_out)
+        return -1;
+    return am1_run(n, nbr, perm_out, exact_out);
 }
 
 /*

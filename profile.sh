@@ -17,6 +17,11 @@
 # texture-addresser, L1-to-L2 and clock counters) over one bench.py job of
 # the 2,097,152-cell workload, for the renumbering kernels and the step.
 # Output rprof_*.  Summarise with python profile_summary.py renumber.
+#
+# `profile.sh orders`: the random / AM1 / Cuthill-McKee comparison on the
+# 512 x 512-quad irregular mesh (tests/test_gpu_irregular.py) under the L2
+# hit and miss counters.  Output oprof_*.  Summarise with
+# python profile_summary.py orders.
 set -euo pipefail
 ROOT="$(cd "$(dirname "$0")" && pwd)"
 OUT="${FV_PROFILE_DIR:-$ROOT/profile_out}"
@@ -35,6 +40,15 @@ if [ "${1:-}" = "renumber" ]; then
     timeout -s KILL 120 rocprofv3 --pmc TA_TA_BUSY TA_ADDR_STALLED_BY_TC_CYCLES TCP_TCC_READ_REQ \
         TCP_TCC_READ_REQ_LATENCY GRBM_GUI_ACTIVE SQ_INSTS_LDS -f csv \
         -d "$OUT/rprof_mem" -o mem -- "${JOB[@]}" > "$OUT/rprof_mem.log" 2>&1
+    echo "[profile] done" >&2
+    exit 0
+fi
+if [ "${1:-}" = "orders" ]; then
+    # the order comparison on the 512 x 512 irregular mesh (a test: AM1 comes
+    # from the CPU reference) under the L2 hit and miss counters
+    echo "[profile] orders: L2 hits and misses per order" >&2
+    timeout -s KILL 600 rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d "$OUT/oprof_l2" -o l2 -- \
+        python3 -m pytest -q -s -m gpu -k orders "$ROOT/tests/test_gpu_irregular.py" > "$OUT/oprof_l2.log" 2>&1
     echo "[profile] done" >&2
     exit 0
 fi

@@ -109,6 +109,36 @@ def main() -> int:
     return 0
 
 
+def main_orders() -> int:
+    """Summary of `profile.sh orders`: the step launches of the comparison
+    come as runs of 20 + 150 (random), 20 + 200 (AM1) and 20 + 250
+    (Cuthill-McKee) launches, in that order (tests/test_gpu_irregular.py
+    COMMON and RUNS)."""
+    path = os.path.join(OUT, "oprof_l2", "l2_counter_collection.csv")
+    rows = [r for r in csv.DictReader(open(path)) if "fv_step_kernel" in r["Kernel_Name"]]
+    per = {}
+    for r in rows:
+        d = per.setdefault(int(r["Dispatch_Id"]), {"name": short(r["Kernel_Name"])})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+    ids = sorted(per)
+    lines = ["| order | step launches | kernel | L2 hits / launch | L2 misses / launch | L2 hit rate |",
+             "|---|---|---|---|---|---|"]
+    k = 0
+    for name, count in (("random", 170), ("AM1", 220), ("Cuthill-McKee", 270)):
+        run = [per[i] for i in ids[k:k + count]]
+        k += count
+        h = st.mean(d["TCC_HIT_sum"] for d in run)
+        m = st.mean(d["TCC_MISS_sum"] for d in run)
+        lines.append(f"| {name} | {len(run)} | {run[0]['name']} | {h:.4g} | {m:.4g} | "
+                     f"{h / (h + m):.3f} |")
+    log = os.path.join(OUT, "oprof_l2.log")
+    if os.path.exists(log):
+        lines.append("")
+        lines += [ln.rstrip() for ln in open(log) if ln.startswith("irregular")]
+    print("\n".join(lines))
+    return 0
+
+
 def main_learned() -> int:
     """Summary of `profile.sh learned`."""
     lines = []
@@ -174,8 +204,11 @@ def main_renumber() -> int:
     sq = per_dispatch(os.path.join(OUT, "rprof_sq", "sq_counter_collection.csv"))
     mem = per_dispatch(os.path.join(OUT, "rprof_mem", "mem_counter_collection.csv"))
     step = "void fv_step_kernel<256, true, true, true>"
-    rows = [("cm_first_kernel", 1, 1366), ("cm_translate_kernel", 256, 0),
-            ("cm_finish_kernel", 1, 1366), (step, 256, 0)]
+    # (kernel, CUs it runs on, levels of its breadth-first sweep): the probe
+    # kernel runs two workgroups (the sweep and the labelling), one CU each
+    rows = [("cm_first_kernel", 1, 1366), ("cm_invert_kernel", 256, 0),
+            ("cm_rename_kernel", 256, 0), ("cm_probe_kernel", 2, 1366),
+            ("cm_finish_kernel", 1, 0), (step, 256, 0)]
     lines = ["| kernel | cycles | waves | VALU / wave | VMEM reads / wave | VALU busy / SIMD "
              "| waves waiting: any / on data | TA busy / stalled by L1 | L1->L2 reads "
              "| L2 read latency (cycles) |",
@@ -208,6 +241,8 @@ def main_renumber() -> int:
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "learned":
         sys.exit(main_learned())
+    if len(sys.argv) > 1 and sys.argv[1] == "orders":
+        sys.exit(main_orders())
     if len(sys.argv) > 1 and sys.argv[1] == "renumber":
         sys.exit(main_renumber())
     sys.exit(main())

@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 from fvgen import ic
-from fvgen.mesh import periodic_mesh, permute_mesh, random_permutation
+from fvgen.mesh import irregular_periodic_mesh, periodic_mesh, permute_mesh, random_permutation
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 G = 1.4
@@ -361,6 +361,64 @@ def pin_bounded_pattern(o, N=16):
     return True, f"AM1 bandwidth {full}"
 
 
+def section41_windows(nbr, perm):
+    """Per label i of the labelling perm (new -> old): e(i), s(i) over the
+    closed neighbourhood, E(i) = max e(1..i), S(i) = min s(i..n) (section 4.1),
+    written here from the definitions."""
+    n = len(perm)
+    lab = np.empty(n, dtype=np.int64)
+    lab[np.asarray(perm)] = np.arange(n)
+    s = np.empty(n, dtype=np.int64)
+    e = np.empty(n, dtype=np.int64)
+    for i, v in enumerate(perm):
+        ls = [i] + [int(lab[w]) for w in nbr[v]]
+        s[i], e[i] = min(ls), max(ls)
+    E = np.maximum.accumulate(e)
+    S = np.minimum.accumulate(s[::-1])[::-1]
+    return s, e, S, E
+
+
+def pin_exact_sbw_golden(o):
+    """Eq. exact-sbw (section 4.3.1) on the hand-worked AM1 runs."""
+    d = _load("bandwidth_cases.json")
+    for c in d["cases"]:
+        if "am1_exact_sbw" in c:
+            _, ex = o.am1_exact_sbw(np.array(c["nbr"], dtype=np.int32))
+            if ex.tolist() != c["am1_exact_sbw"]:
+                return False, f"{c['name']}: {ex.tolist()} != {c['am1_exact_sbw']}"
+    return True, "hand-worked cases"
+
+
+def pin_exact_sbw_is_the_definition(o):
+    """The paper states that Eq. exact-sbw equals the serial bandwidth of
+    section 4.1: AM1 always takes a node of u(I), so the union of u(k),
+    I <= k <= i, receives the next labels and node(i)'s window ends at
+    E(i); hence exact(i) = E(i) - s(i) of the final labelling wherever it is
+    defined, and the largest E(i) - s(i) is S_BW = max E(i) - S(i)."""
+    graphs = []
+    for N, seed in ((6, 2), (9, 3)):
+        m = periodic_mesh(N)
+        graphs.append(permute_mesh(m, random_permutation(m.n, seed)).nbr)
+    for N, seed in ((8, 4), (12, 5)):
+        m = irregular_periodic_mesh(N, seed=seed)
+        graphs.append(permute_mesh(m, random_permutation(m.n, seed)).nbr)
+    for nbr in graphs:
+        perm, ex = o.am1_exact_sbw(nbr)
+        s, e, S, E = section41_windows(nbr, perm)
+        own = E - s
+        defined = ex >= 0
+        if not np.array_equal(ex[defined], own[defined]):
+            k = int(np.flatnonzero(ex[defined] != own[defined])[0])
+            return False, f"n={len(perm)}: exact {ex[defined][k]} vs E - s {own[defined][k]}"
+        lab = np.empty(len(perm), dtype=np.int32)
+        lab[perm] = np.arange(len(perm), dtype=np.int32)
+        sbw = o.bandwidth(nbr, lab)["S_BW"]
+        if not (int(own.max()) == int(np.max(E - S)) == sbw and int(ex.max()) <= sbw):
+            return False, f"n={len(perm)}: max E - s {own.max()}, S_BW {sbw}, max exact {ex.max()}"
+    return True, f"{len(graphs)} graphs"
+
+
 QUICK_PINS = [pin_golden_faces, pin_consistency, pin_xy_form, pin_antisymmetry, pin_conservation,
               pin_freestream, pin_translation, pin_stability, pin_contact_advection, pin_cm_golden,
-              pin_am1_golden, pin_bandwidth_golden, pin_bounded_pattern]
+              pin_am1_golden, pin_bandwidth_golden, pin_bounded_pattern, pin_exact_sbw_golden,
+              pin_exact_sbw_is_the_definition]

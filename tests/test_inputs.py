@@ -4,7 +4,8 @@ import numpy as np
 import pytest
 
 from fvgen import ic
-from fvgen.mesh import periodic_mesh, permute_mesh, random_permutation, shuffled_periodic_mesh
+from fvgen.mesh import (irregular_periodic_mesh, periodic_mesh, permute_mesh, random_permutation,
+                        shuffled_periodic_mesh)
 
 
 @pytest.mark.parametrize("N", [2, 3, 8, 37])
@@ -24,6 +25,41 @@ def test_mesh_reciprocal_and_exact(N):
     assert np.all(m.nrm.sum(axis=1) == 0.0)
     # coordinates snapped to the 2^-32 grid
     assert np.all(m.verts * 2.0**32 == np.round(m.verts * 2.0**32))
+
+
+@pytest.mark.parametrize("N,seed,refine", [(4, 1, None), (12, 2, None), (33, 3, None),
+                                           (16, 4, (3.0, 7.0, 2.0, 2))])
+def test_irregular_mesh_reciprocal_exact_and_irregular(N, seed, refine):
+    """The irregular-topology mesh keeps every exactness property of the
+    structured one, while its vertex degrees vary (the structured split has
+    degree 6 at every vertex)."""
+    m = irregular_periodic_mesh(N, seed=seed, refine=refine)
+    h = m.L / N
+    if refine is None:
+        assert m.n == 2 * N * N
+        assert np.all(m.area >= 0.05 * h * h * (1 - 1e-12))
+    else:
+        # each split turns one cell into three: refined cells are far smaller
+        assert m.n > 2 * N * N and (m.n - 2 * N * N) % 2 == 0
+        assert np.all(m.area > 0) and m.area.max() / m.area.min() > 50
+    assert m.area.sum() == pytest.approx(m.L * m.L, rel=1e-13)
+    for i in range(m.n):
+        for f in range(3):
+            j = m.nbr[i, f]
+            assert j != i
+            hits = [g for g in range(3) if m.nbr[j, g] == i and np.all(m.nrm[j, g] == -m.nrm[i, f])]
+            assert len(hits) >= 1
+    assert np.all(m.nrm.sum(axis=1) == 0.0)
+    assert np.all(m.verts * 2.0**32 == np.round(m.verts * 2.0**32))
+    # vertex degree = number of triangles around a vertex (each corner of a
+    # cell is a vertex; wrap coordinates to identify periodic copies)
+    key = np.round((m.verts % m.L) * 2.0**32).astype(np.int64).reshape(-1, 2)
+    _, counts = np.unique(key, axis=0, return_counts=True)
+    assert counts.sum() == 3 * m.n
+    if N >= 12:
+        assert counts.min() <= 4 and counts.max() >= 8, (counts.min(), counts.max())
+    again = irregular_periodic_mesh(N, seed=seed, refine=refine)
+    assert np.array_equal(again.nbr, m.nbr) and np.array_equal(again.nrm, m.nrm)
 
 
 def test_jitter_bounds_and_seed():

@@ -41,6 +41,10 @@ MUTATIONS = {
     "AM1 ties go to the larger id": ("(score == best_score && k < best)",
                                      "(score == best_score && k > best)"),
     "AM1 scores node(I) too": ("if (p >= 0 && knb[g] != vI)", "if (p >= 0)"),
+    "exact S_BW counts the union with repeats": ("if (pos[kn[g]] < 0 && seen[kn[g]] != m) {",
+                                                 "if (pos[kn[g]] < 0) {"),
+    "exact S_BW without s(i)": ("exact_out[m] = (size - 1 - m) + un + sv[m];",
+                                "exact_out[m] = (size - 1 - m) + un;"),
     "bounded pattern ignores its stop rule": ("if (max_imp > bound && I > 0)",
                                               "if (max_imp > bound + 1000000 && I > 0)"),
     "bounded pattern executes node(I) too": ("const int run = k < I && !ghost[k];",
