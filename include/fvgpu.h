@@ -169,7 +169,12 @@ fv_status fv_step_batch(fv_ctx *ctx, int32_t n_steps, const double *dt);
  * all meshes use this dt.
  *   d_U       device double [n][4], numbering of the uploaded mesh, 32-byte aligned.
  *   d_lambda  device double [n][4], same numbering, in/out, 32-byte aligned.
- * Asynchronous on the stream; uses the context's scratch memory.
+ * The adjoint runs on the working (renumbered) geometry, as fv_step does: U
+ * and lambda are gathered into the working order and each cell's result is
+ * written back to its place in the uploaded numbering, so each cell's result
+ * does not depend on the renumbering.  Asynchronous on the stream; uses the
+ * context's scratch memory and its spare state buffer (the current state is
+ * kept).
  */
 fv_status fv_step_adjoint(fv_ctx *ctx, const double *d_U, double *d_lambda, double dt);
 
@@ -180,8 +185,9 @@ fv_status fv_step_adjoint(fv_ctx *ctx, const double *d_U, double *d_lambda, doub
  *   d_grad  device double [FV_CORRECTION_PARAMS], 8-byte aligned, in/out;
  *           NULL makes this fv_step_adjoint.
  * FV_ESTATE if d_grad is given and no correction is set.  The sum over the
- * cells is taken in a fixed order for a given mesh size, so repeated calls
- * give the same bits.  Asynchronous on the stream.
+ * cells is taken in a fixed order (the working order) for a given mesh and
+ * renumbering, so repeated calls give the same bits.  Asynchronous on the
+ * stream.
  */
 fv_status fv_step_adjoint_grad(fv_ctx *ctx, const double *d_U, double *d_lambda, double dt,
                                double *d_grad);

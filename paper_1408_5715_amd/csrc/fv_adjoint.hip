@@ -23,22 +23,23 @@ using namespace dual;
 
 __global__ __launch_bounds__(256) void adjoint_kernel(
     int32_t n, int32_t ld, const double4 *__restrict__ U, const double4 *__restrict__ lam_next,
-    double4 *__restrict__ lam, const int32_t *__restrict__ nb, const double *__restrict__ nrm,
-    const double *__restrict__ area, double dt, double gamma)
+    double4 *__restrict__ lam, const int32_t *__restrict__ out_idx,
+    const int32_t *__restrict__ nb, const double *__restrict__ nrm,
+    const double *__restrict__ inv_area, double dt, double gamma)
 {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= n)
         return;
     const double4 Uk = U[k];
     const double4 lk = lam_next[k];
-    const double ck = step_coef(dt, area[k]);
+    const double ck = step_coef(dt, inv_area[k]);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
         const int j = nb[f * ld + k];
         const double nx = nrm[(2 * f) * ld + k], ny = nrm[(2 * f + 1) * ld + k];
         const double4 lj = lam_next[j];
-        const double cj = step_coef(dt, area[j]);
+        const double cj = step_coef(dt, inv_area[j]);
         const double v[4] = {ck * lk.x - cj * lj.x, ck * lk.y - cj * lj.y, ck * lk.z - cj * lj.z,
                              ck * lk.w - cj * lj.w};
         flux_vjp(Uk, U[j], nx, ny, gamma, v, acc);
@@ -48,19 +49,20 @@ __global__ __launch_bounds__(256) void adjoint_kernel(
     out.y = lk.y - acc[1];
     out.z = lk.z - acc[2];
     out.w = lk.w - acc[3];
-    lam[k] = out;
+    lam[out_idx[k]] = out;
 }
 
 }  // namespace
 
 hipError_t launch_adjoint(int32_t n, int32_t ld, const double4 *U, const double4 *lam_next,
-                          double4 *lam, const int32_t *nb, const double *nrm, const double *area,
-                          double dt, double gamma, hipStream_t s)
+                          double4 *lam, const int32_t *out_idx, const int32_t *nb,
+                          const double *nrm, const double *inv_area, double dt, double gamma,
+                          hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(adjoint_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ld, U,
-                       lam_next, lam, nb, nrm, area, dt, gamma);
+                       lam_next, lam, out_idx, nb, nrm, inv_area, dt, gamma);
     return hipGetLastError();
 }
 

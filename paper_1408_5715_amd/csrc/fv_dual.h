@@ -97,10 +97,11 @@ __device__ __forceinline__ void flux_vjp(const double4 &UL, const double4 &UR, d
         acc[q] += F[0].d[q] * v[0] + F[1].d[q] * v[1] + F[2].d[q] * v[2] + F[3].d[q] * v[3];
 }
 
-// c_k = dt * (1 / V_k), rounded exactly as the forward step forms it.
-__device__ __forceinline__ double step_coef(double dt, double area)
+// c_k = dt * (1 / V_k) from the stored 1 / V_k, rounded exactly as the
+// forward step forms it.
+__device__ __forceinline__ double step_coef(double dt, double inv_area)
 {
-    return dt * (1.0 / area);
+    return dt * inv_area;
 }
 
 }  // namespace dual

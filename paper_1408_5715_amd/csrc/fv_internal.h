@@ -45,12 +45,15 @@ hipError_t launch_narrow_offsets(int32_t n, int32_t ld, const int32_t *nb, short
                                  int32_t *too_far, hipStream_t s);
 
 // Cotangent of one step's input from the cotangent of its output, on arrays
-// in any one numbering (mesh arrays nb [3][ld], nrm [6][ld], area [ld]):
+// in any one numbering (mesh arrays nb [3][ld], nrm [6][ld], inv_area [ld]
+// holding 1 / V):
 // lam = lam_next - sum_f (dG(U_k, U_j, n_f)/dU_k)^T (c_k lam_next_k - c_j lam_next_j),
-// c = dt * (1 / area).  lam and lam_next must not overlap.
+// c = dt * (1 / V), rounded as the step forms it.  Cell k's result goes to
+// lam[out_idx[k]] (out_idx a permutation); lam and lam_next must not overlap.
 hipError_t launch_adjoint(int32_t n, int32_t ld, const double4 *U, const double4 *lam_next,
-                          double4 *lam, const int32_t *nb, const double *nrm, const double *area,
-                          double dt, double gamma, hipStream_t s);
+                          double4 *lam, const int32_t *out_idx, const int32_t *nb,
+                          const double *nrm, const double *inv_area, double dt, double gamma,
+                          hipStream_t s);
 
 // Learned correction: the packed MLP (weight fragments, kCorrFragShorts
 // bfloat16, then 144 float biases: b1, b2, b3 padded to 16) and the step that
@@ -66,18 +69,20 @@ hipError_t launch_step_learned(int32_t n, int32_t ld, const double4 *U, double4 
                                hipStream_t s);
 
 // Adjoint of the corrected step (see fv_learned.hip): lam from lam_next as
-// launch_adjoint does, plus the cotangent of the correction, on arrays in
-// any one numbering.  Each workgroup leaves its part of the parameter
-// gradient in partial [adjoint_learned_grid(n)][kCorrParams]; with grad
-// non-null, grad [kCorrParams] (float64) += the gradient.
+// launch_adjoint does (same arrays, output through out_idx), plus the
+// cotangent of the correction, on arrays in any one numbering; the parameter
+// gradient sums the cells in that numbering.  Each workgroup leaves its part
+// of the parameter gradient in partial [adjoint_learned_grid(n)][kCorrParams];
+// with grad non-null, grad [kCorrParams] (float64) += the gradient.
 constexpr int kCorrAdjFragShorts = (4 * 4 + 8 * 8 + 4 * 4 + 8 * 8 + 2 * 8) * 64;
 constexpr int kCorrAdjMaxGrid = 512;
 void pack_correction_adjoint(const float *params, short *afrags);
 int adjoint_learned_grid(int32_t n);
 hipError_t launch_adjoint_learned(int32_t n, int32_t ld, const double4 *U, const double4 *lam_next,
-                                  double4 *lam, const int32_t *nb, const double *nrm,
-                                  const double *area, double dt, double gamma, const short *afrags,
-                                  const float *bias, float *partial, double *grad, hipStream_t s);
+                                  double4 *lam, const int32_t *out_idx, const int32_t *nb,
+                                  const double *nrm, const double *inv_area, double dt,
+                                  double gamma, const short *afrags, const float *bias,
+                                  float *partial, double *grad, hipStream_t s);
 
 // ---- renumbering --------------------------------------------------------
 // rec[v] = (nb_0[v], nb_1[v], nb_2[v], -1): the graph with an empty label slot.

@@ -576,9 +576,10 @@ __device__ __forceinline__ void mlp_adjoint_rows(const short *Af, const float *B
 
 __global__ __launch_bounds__(kBlock) void fv_adjoint_learned_kernel(
     int32_t n, int32_t ld, const double4 *__restrict__ U, const double4 *__restrict__ lam_next,
-    double4 *__restrict__ lam, const int32_t *__restrict__ nb, const double *__restrict__ nrm,
-    const double *__restrict__ area, double dt, double gamma, const short *__restrict__ afrags,
-    const float *__restrict__ bias, float *__restrict__ partial)
+    double4 *__restrict__ lam, const int32_t *__restrict__ out_idx,
+    const int32_t *__restrict__ nb, const double *__restrict__ nrm,
+    const double *__restrict__ inv_area, double dt, double gamma,
+    const short *__restrict__ afrags, const float *__restrict__ bias, float *__restrict__ partial)
 {
     __shared__ __attribute__((aligned(16))) short Xs[kWaves][64 * kXStride];
     __shared__ __attribute__((aligned(16))) short Ws[kWaves][64 * kWcStride];
@@ -624,8 +625,8 @@ __global__ __launch_bounds__(kBlock) void fv_adjoint_learned_kernel(
         if (live) {
             Uk = U[k];
             lk = lam_next[k];
-            ak = 1.0 / area[k];
-            ck = dual::step_coef(dt, area[k]);
+            ak = inv_area[k];
+            ck = dual::step_coef(dt, inv_area[k]);
         }
         const Side L = side_of(Uk, gamma);
         double accU[4] = {0.0, 0.0, 0.0, 0.0};
@@ -637,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void fv_adjoint_learned_kernel(
                 const double nx = nrm[(2 * f) * ld + k], ny = nrm[(2 * f + 1) * ld + k];
                 const double4 Uj = U[j];
                 const double4 lj = lam_next[j];
-                const double aj = 1.0 / area[j], cj = dual::step_coef(dt, area[j]);
+                const double aj = inv_area[j], cj = dual::step_coef(dt, inv_area[j]);
                 const double v[4] = {ck * lk.x - cj * lj.x, ck * lk.y - cj * lj.y,
                                      ck * lk.z - cj * lj.z, ck * lk.w - cj * lj.w};
                 dual::flux_vjp(Uk, Uj, nx, ny, gamma, v, accU);
@@ -688,7 +689,7 @@ __global__ __launch_bounds__(kBlock) void fv_adjoint_learned_kernel(
             out.y = lk.y - accU[1];
             out.z = lk.z - accU[2];
             out.w = lk.w - accU[3];
-            lam[k] = out;
+            lam[out_idx[k]] = out;
         }
     }
 
@@ -853,15 +854,16 @@ int adjoint_learned_grid(int32_t n)
 }
 
 hipError_t launch_adjoint_learned(int32_t n, int32_t ld, const double4 *U, const double4 *lam_next,
-                                  double4 *lam, const int32_t *nb, const double *nrm,
-                                  const double *area, double dt, double gamma, const short *afrags,
-                                  const float *bias, float *partial, double *grad, hipStream_t s)
+                                  double4 *lam, const int32_t *out_idx, const int32_t *nb,
+                                  const double *nrm, const double *inv_area, double dt,
+                                  double gamma, const short *afrags, const float *bias,
+                                  float *partial, double *grad, hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
     const int G = adjoint_learned_grid(n);
     hipLaunchKernelGGL(fv_adjoint_learned_kernel, dim3(G), dim3(kBlock), 0, s, n, ld, U, lam_next,
-                       lam, nb, nrm, area, dt, gamma, afrags, bias, partial);
+                       lam, out_idx, nb, nrm, inv_area, dt, gamma, afrags, bias, partial);
     if (grad)
         hipLaunchKernelGGL(grad_reduce_kernel, dim3((kCorrParams + 255) / 256), dim3(256), 0, s,
                            partial, G, -0.5, grad);

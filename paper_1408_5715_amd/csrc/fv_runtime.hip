@@ -673,18 +673,24 @@ fv_status fv_step_adjoint_grad(fv_ctx *c, const double *d_U, double *d_lambda, d
         return fail(FV_EINVAL, "gradient array must be 8-byte aligned");
     if (d_grad && !c->corr_on)
         return fail(FV_ESTATE, "no correction is set: there is no parameter gradient");
-    double4 *out = reinterpret_cast<double4 *>(c->scratch);
+    // The adjoint runs on the working (renumbered) geometry, like the step:
+    // U and lambda are gathered into the working order (the spare state
+    // buffer and the scratch memory), and each cell's result is written back
+    // to its place in the uploaded numbering.
+    double4 *Uw = c->U[c->cur ^ 1];
+    double4 *lw = reinterpret_cast<double4 *>(c->scratch);
+    HIP_TRY(fvk::launch_gather_state(c->n, c->perm, reinterpret_cast<const double4 *>(d_U), Uw,
+                                     c->stream));
+    HIP_TRY(fvk::launch_gather_state(c->n, c->perm, reinterpret_cast<const double4 *>(d_lambda),
+                                     lw, c->stream));
+    double4 *out = reinterpret_cast<double4 *>(d_lambda);
     if (c->corr_on)
-        HIP_TRY(fvk::launch_adjoint_learned(
-            c->n, c->ld, reinterpret_cast<const double4 *>(d_U),
-            reinterpret_cast<const double4 *>(d_lambda), out, c->nb_o, c->nrm_o, c->area_o, dt,
-            c->gamma, c->corr_afrags, c->corr_bias, c->corr_partial, d_grad, c->stream));
+        HIP_TRY(fvk::launch_adjoint_learned(c->n, c->ld, Uw, lw, out, c->perm, c->nb_w, c->nrm_w,
+                                            c->inv_area_w, dt, c->gamma, c->corr_afrags,
+                                            c->corr_bias, c->corr_partial, d_grad, c->stream));
     else
-        HIP_TRY(fvk::launch_adjoint(c->n, c->ld, reinterpret_cast<const double4 *>(d_U),
-                                    reinterpret_cast<const double4 *>(d_lambda), out, c->nb_o,
-                                    c->nrm_o, c->area_o, dt, c->gamma, c->stream));
-    HIP_TRY(hipMemcpyAsync(d_lambda, out, (size_t)c->n * sizeof(double4), hipMemcpyDeviceToDevice,
-                           c->stream));
+        HIP_TRY(fvk::launch_adjoint(c->n, c->ld, Uw, lw, out, c->perm, c->nb_w, c->nrm_w,
+                                    c->inv_area_w, dt, c->gamma, c->stream));
     return FV_OK;
 }
 

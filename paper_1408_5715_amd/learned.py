@@ -281,8 +281,9 @@ def compare_levels(params, N: int, seeds, horizons, cfl: float = 0.8) -> dict:
     4N x 4N reference, all from the reference's initial state restricted to
     each mesh; L2 density errors against the reference restricted to N x N
     after each number of coarse steps in `horizons` (2 and 4 substeps per
-    coarse step on the finer meshes).  Answers whether the corrected coarse
-    solver reaches the 2N solver's accuracy."""
+    coarse step on the finer meshes), and of both coarse solvers against the
+    restricted 2N solution.  Answers whether the corrected coarse solver
+    reaches the 2N solver's accuracy."""
     import torch
 
     from fvgen.nested import nested_pair
@@ -336,7 +337,10 @@ def compare_levels(params, N: int, seeds, horizons, cfl: float = 0.8) -> dict:
             Ec = run(cs, U0c, 1, 4 * dt_r, None, params)
             for q, k in enumerate(horizons):
                 rec = {"seed": int(seed), "steps": k, "coarse_plain": err(Ep[q], T[q]),
-                       "coarse_corrected": err(Ec[q], T[q]), "fine_plain": err(Em[q], T[q])}
+                       "coarse_corrected": err(Ec[q], T[q]), "fine_plain": err(Em[q], T[q]),
+                       # against the restricted 2N x 2N plain solution instead
+                       "coarse_plain_vs_fine": err(Ep[q], Em[q]),
+                       "coarse_corrected_vs_fine": err(Ec[q], Em[q])}
                 out["flows"].append(rec)
                 _log(f"N={N} seed {seed} {k} steps, L2 density error vs the {4 * N}x{4 * N} "
                      f"reference: coarse plain {rec['coarse_plain']:.3e}, coarse corrected "
