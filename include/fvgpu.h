@@ -140,8 +140,26 @@ fv_status fv_upload_state_device(fv_ctx *ctx, const double *d_U);
  *   perm_out  nullable host int32 [n]: perm_out[new] = uploaded id.
  * The state (if uploaded) is carried over.  Results of fv_step do not
  * depend on the order (bitwise).  Synchronises the stream.
+ *
+ * With FV_ORDER_CM and perm_out NULL the call does not wait for the search's
+ * confirming sweep (the level structure from the first candidate, which only
+ * decides whether the search moves on).  The labels assume that it does not,
+ * the sweep runs on a second stream of the context while the caller's work
+ * (typically fv_step) proceeds, and the check is made at the next call that
+ * needs it: fv_renumber_passes, fv_working_order, fv_download_state,
+ * fv_upload_state, fv_step_adjoint(_grad), fv_upload_mesh/batch, fv_renumber
+ * and fv_destroy wait for the sweep.  If some search would have moved, the
+ * first four of these relabel exactly as the sequential search does before
+ * they go on.  The state keeps its values, since fv_step gives the same bits
+ * in any order, so the only visible effect is the working order until then.
  */
 fv_status fv_renumber(fv_ctx *ctx, int32_t method, int32_t *perm_out);
+
+/*
+ * The working (renumbered) order: perm_out[new] = uploaded id, host int32
+ * [n], after any pending check of fv_renumber.  Synchronises the stream.
+ */
+fv_status fv_working_order(fv_ctx *ctx, int32_t *perm_out);
 
 /*
  * Advance n_steps forward-Euler steps of size dt (section 6.2.2, eqFWEuler

@@ -39,5 +39,6 @@ from .fvgpu import (  # noqa: F401
     fv_upload_mesh,
     fv_upload_state,
     fv_upload_state_device,
+    fv_working_order,
     lib,
 )

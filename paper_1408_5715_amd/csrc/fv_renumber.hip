@@ -799,15 +799,20 @@ __device__ __forceinline__ void label_levels(const int4 *__restrict__ g,
 //   cm_invert_kernel,    the component's graph renamed by that order (rec2:
 //   cm_rename_kernel     neighbours as positions), in which every level is a
 //                        contiguous range;
-//   cm_probe_kernel      two workgroups per segment, side by side: the sweep
-//                        from the pick on rec2 (the search's second step),
-//                        and the labels from the first sweep's levels
+//   cm_probe_kernel      the sweep from the pick on rec2 (the search's
+//                        second step), on a second stream, beside
+//   cm_label_kernel      the labels from the first sweep's levels
 //                        (label_levels), which are the result when the
 //                        eccentricity does not grow (the root then stays
 //                        the lowest id);
 //   cm_finish_kernel     otherwise, and for every later component, the
 //                        search continues with full labelling passes on the
-//                        uploaded graph (cm_pass).
+//                        uploaded graph (cm_pass).  With assume_stays the
+//                        finish does not wait for the probe: it takes the
+//                        labels of cm_label_kernel and goes on with the later
+//                        components; the caller checks the probe's
+//                        eccentricities afterwards and relabels exactly if
+//                        some search would have moved.
 //
 // cm_first_kernel: state[s] = (cells reached, eccentricity, pick, widest level).
 __global__ __launch_bounds__(kCmThreads) void cm_first_kernel(int4 *__restrict__ rec,
@@ -842,10 +847,13 @@ __device__ __forceinline__ int segment_of(int l, int n_seg, const int64_t *__res
     return lo;
 }
 
-// inv[ordA[l]] = l for the positions l of each segment's first component.
+// inv[ordA[l]] = l for the positions l of each segment's first component;
+// root[s] = the position of the segment's pick (the probe sweep's root, which
+// the probe kernel reads from here rather than from inv, which the final
+// inverse overwrites on the other stream).
 __global__ void cm_invert_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict__ seg,
                                  const int4 *__restrict__ state, const int32_t *__restrict__ ordA,
-                                 int32_t *__restrict__ inv)
+                                 int32_t *__restrict__ inv, int32_t *__restrict__ root)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= n)
@@ -853,7 +861,10 @@ __global__ void cm_invert_kernel(int32_t n, int32_t n_seg, const int64_t *__rest
     const int sg = segment_of(l, n_seg, seg);
     if (l - (int)seg[sg] >= state[sg].x)
         return;
-    inv[ordA[l]] = l;
+    const int c = ordA[l];
+    inv[c] = l;
+    if (c == state[sg].z)
+        root[sg] = l;
 }
 
 // rec2[l] = (positions of the three neighbours of the cell at position l, -1)
@@ -873,31 +884,48 @@ __global__ void cm_rename_kernel(int32_t n, int32_t n_seg, const int64_t *__rest
     rec2[l] = make_int4(inv[r.x], inv[r.y], inv[r.z], -1);
 }
 
-// Grid (n_seg, 2).  Workgroup y = 0: the sweep from the first component's
-// pick on rec2; probe[s] = its eccentricity.  Workgroup y = 1: the labels of
-// the first component from the first sweep's levels into perm, when every
-// level fits in LDS (the finish kernel discards them if the search moves).
+// The sweep from the first component's pick on rec2, one workgroup per
+// segment: on entry probe[s] holds the pick's position (cm_invert_kernel), on
+// exit the sweep's eccentricity.  It may run beside the label and finish
+// kernels, so it writes only rec2's marks, its own order ordC and probe, and
+// reads nothing they write (the pick it finds is not used).
 __global__ __launch_bounds__(kCmThreads) void cm_probe_kernel(
-    int4 *__restrict__ rec2, const int64_t *__restrict__ seg, const int4 *__restrict__ state,
-    const int32_t *__restrict__ ordA, const int32_t *__restrict__ levA,
-    const int32_t *__restrict__ inv, int32_t *__restrict__ ordB, int32_t *__restrict__ perm,
+    int4 *__restrict__ rec2, const int64_t *__restrict__ seg, int32_t *__restrict__ ordC,
     int32_t *__restrict__ probe)
 {
-    __shared__ union {
-        BfsLds bfs;
-        LabelLds label;
-    } lds;
+    __shared__ BfsLds lds;
+    const int s0 = (int)seg[blockIdx.x], s1 = (int)seg[blockIdx.x + 1];
+    if (s0 >= s1)
+        return;
+    const int root = probe[blockIdx.x];
+    if (root < s0 || root >= s1) {  // block-uniform; cannot happen (the pick is in the component)
+        __syncthreads();
+        if (threadIdx.x == 0)
+            probe[blockIdx.x] = INT_MAX;  // makes the finish run the exact search
+        return;
+    }
+    const BfsResult r = bfs_pass(rec2, root, s0, ordC, nullptr, nullptr, lds);
+    __syncthreads();  // every thread has read probe[] before it is overwritten
+    if (threadIdx.x == 0)
+        probe[blockIdx.x] = r.ecc;
+}
+
+// The labels of each segment's first component from the first sweep's levels
+// into perm, when every level fits in LDS (the finish kernel discards them if
+// the search moves).  Reads only the (x, y, z) fields of rec2, which the probe
+// sweep may run beside it.
+__global__ __launch_bounds__(kCmThreads) void cm_label_kernel(
+    const int4 *__restrict__ rec2, const int64_t *__restrict__ seg,
+    const int4 *__restrict__ state, const int32_t *__restrict__ ordA,
+    const int32_t *__restrict__ levA, int32_t *__restrict__ perm)
+{
+    __shared__ LabelLds lds;
     const int s0 = (int)seg[blockIdx.x], s1 = (int)seg[blockIdx.x + 1];
     if (s0 >= s1)
         return;
     const int4 st = state[blockIdx.x];
-    if (blockIdx.y == 0) {
-        const BfsResult r = bfs_pass(rec2, inv[st.z], s0, ordB, nullptr, ordA, lds.bfs);
-        if (threadIdx.x == 0)
-            probe[blockIdx.x] = r.ecc;
-    } else if (st.w <= kLabelCap) {
-        label_levels(rec2, ordA, levA, s0, st.x, st.y, perm, lds.label);
-    }
+    if (st.w <= kLabelCap)
+        label_levels(rec2, ordA, levA, s0, st.x, st.y, perm, lds);
 }
 
 // The rest of the search for every segment, after cm_probe_kernel, as one
@@ -912,7 +940,7 @@ __global__ __launch_bounds__(kCmThreads) void cm_probe_kernel(
 __global__ __launch_bounds__(kCmThreads) void cm_finish_kernel(
     int4 *__restrict__ rec, const int64_t *__restrict__ seg, const int4 *__restrict__ state,
     const int32_t *__restrict__ probe, int32_t *__restrict__ permA, int32_t *__restrict__ permB,
-    int32_t *__restrict__ perm, int32_t *__restrict__ passes)
+    int32_t *__restrict__ perm, int32_t *__restrict__ passes, int32_t assume_stays)
 {
     enum { kRoot, kSearch };
     __shared__ PassLds lds;
@@ -930,7 +958,7 @@ __global__ __launch_bounds__(kCmThreads) void cm_finish_kernel(
     int scan_from = s0;
     int mode = kRoot;
     if (s0 < s1) {
-        if (probe[blockIdx.x] > rr.ecc) {
+        if (!assume_stays && probe[blockIdx.x] > rr.ecc) {
             mode = kSearch;  // relabel exactly from the same pick
         } else {
             if (st.w > kLabelCap) {
@@ -1048,8 +1076,9 @@ hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *
 
 hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe, int32_t n,
                               int32_t n_seg, const int64_t *seg, int32_t *permA, int32_t *permB,
-                              int32_t *levA, int32_t *perm, int32_t *label, int32_t *passes,
-                              hipStream_t s)
+                              int32_t *ordC, int32_t *levA, int32_t *perm, int32_t *label,
+                              int32_t *passes, hipStream_t s, hipStream_t side,
+                              hipEvent_t renamed, hipEvent_t probed, bool speculative)
 {
     hipLaunchKernelGGL(cm_first_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, seg, permA,
                        levA, state);
@@ -1059,7 +1088,7 @@ hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe
     // label serves as the inverse of the first order until invert_kernel
     // writes the final one
     hipLaunchKernelGGL(cm_invert_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, n_seg, seg,
-                       state, permA, label);
+                       state, permA, label, probe);
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
@@ -1068,13 +1097,25 @@ hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(cm_probe_kernel, dim3(n_seg, 2), dim3(kCmThreads), 0, s, rec2, seg, state,
-                       permA, levA, label, permB, perm, probe);
-    e = hipGetLastError();
-    if (e != hipSuccess)
+    // the probe sweep on the second stream, the labels on this one
+    if ((e = hipEventRecord(renamed, s)) != hipSuccess)
+        return e;
+    if ((e = hipStreamWaitEvent(side, renamed, 0)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(cm_probe_kernel, dim3(n_seg), dim3(kCmThreads), 0, side, rec2, seg, ordC,
+                       probe);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if ((e = hipEventRecord(probed, side)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(cm_label_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec2, seg, state,
+                       permA, levA, perm);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if (!speculative && (e = hipStreamWaitEvent(s, probed, 0)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(cm_finish_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, seg, state,
-                       probe, permA, permB, perm, passes);
+                       probe, permA, permB, perm, passes, (int32_t)speculative);
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;

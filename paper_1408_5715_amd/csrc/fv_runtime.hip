@@ -72,7 +72,8 @@ struct Layout {
         area = align_up(ld * 8);
         idx = align_up(ld * 4);
         // >= AoS normals (48 B), state (32 B), renumbering scratch (records,
-        // two orders, renamed records, level starts: 44 B)
+        // two orders, renamed records, level starts, the confirming sweep's
+        // order: 48 B)
         scratch = align_up(ld * 48);
         // segment offsets (int64), per-segment dt (double), per-segment pass
         // counts (int32), per-segment first-sweep results (int4) and
@@ -133,6 +134,10 @@ struct fv_ctx {
     short *corr_afrags = nullptr;   // fragments of the adjoint kernel
     float *corr_partial = nullptr;  // per-workgroup parameter gradients
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
+    hipStream_t side = nullptr;        // second stream of the renumbering (default priority)
+    hipEvent_t ev_renamed = nullptr;   // renamed graph ready (recorded on `stream`)
+    hipEvent_t ev_probed = nullptr;    // confirming sweep done (recorded on `side`)
+    bool probe_pending = false;        // a speculative renumbering's confirming sweep is unchecked
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     long long graph_key[6] = {-1, -1, -1, -1, -1, -1};
@@ -254,12 +259,26 @@ fv_status regather_geometry(fv_ctx *c)
     return FV_OK;
 }
 
+// The renumbering's second stream and its two events, created on first use.
+fv_status ensure_side(fv_ctx *c)
+{
+    if (!c->side)
+        HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    if (!c->ev_renamed)
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_renamed, hipEventDisableTiming));
+    if (!c->ev_probed)
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_probed, hipEventDisableTiming));
+    return FV_OK;
+}
+
 // Cuthill-McKee labelling of every segment of the uploaded graph into
-// c->perm / c->label, one workgroup per segment, all on the device.
-// Scratch use (bytes per cell): records 16, two orders 4 + 4, renamed
-// records 16, level starts 4 (ld is a multiple of 64, so every part stays
+// c->perm / c->label, one workgroup per segment, all on the device (the
+// confirming sweep of the root search on the second stream; see
+// launch_cm_segments for `speculative`).  Scratch use (bytes per cell):
+// records 16, two orders 4 + 4, renamed records 16, level starts 4, the
+// confirming sweep's order 4 (ld is a multiple of 64, so every part stays
 // aligned).
-fv_status cm_order(fv_ctx *c)
+fv_status cm_order(fv_ctx *c, bool speculative)
 {
     const int32_t n = c->n;
     const size_t ld = (size_t)c->ld;
@@ -268,10 +287,13 @@ fv_status cm_order(fv_ctx *c)
     int32_t *permB = permA + ld;
     int4 *rec2 = reinterpret_cast<int4 *>(permB + ld);
     int32_t *levA = reinterpret_cast<int32_t *>(rec2 + ld);
+    int32_t *ordC = levA + ld;
+    if (fv_status st = ensure_side(c))
+        return st;
     HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
     HIP_TRY(fvk::launch_cm_segments(rec, rec2, c->cm_state, c->cm_probe, n, c->n_seg, c->seg_dev,
-                                    permA, permB, levA, c->perm, c->label, c->passes_dev,
-                                    c->stream));
+                                    permA, permB, ordC, levA, c->perm, c->label, c->passes_dev,
+                                    c->stream, c->side, c->ev_renamed, c->ev_probed, speculative));
     return FV_OK;
 }
 
@@ -359,6 +381,67 @@ fv_status run_steps(fv_ctx *c, int32_t n_steps)
     }
     HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
     c->cur ^= (n_steps & 1);
+    return FV_OK;
+}
+
+// A renumbering of the mesh into c->perm / c->label and the working
+// geometry; the state, if any, follows into the new order.  The state moves
+// to the uploaded order in the spare buffer, then to the new order in the
+// current one.  Speculative (Cuthill-McKee only): the labels assume that no
+// pseudo-peripheral search moves beyond its first candidate, and the
+// confirming sweep is left running on the second stream (see settle).
+fv_status renumber_now(fv_ctx *c, int32_t method, bool speculative)
+{
+    double4 *spare = c->U[c->cur ^ 1];
+    if (c->state_ready)
+        HIP_TRY(fvk::launch_gather_state(c->n, c->label, c->U[c->cur], spare, c->stream));
+    c->cm_passes = false;
+    if (method == FV_ORDER_IDENTITY) {
+        HIP_TRY(fvk::launch_iota(c->perm, c->n, c->stream));
+        HIP_TRY(fvk::launch_iota(c->label, c->n, c->stream));
+    } else {
+        if (fv_status st = cm_order(c, speculative))
+            return st;
+        c->cm_passes = true;
+    }
+    if (fv_status st = regather_geometry(c))
+        return st;
+    if (c->state_ready)
+        HIP_TRY(fvk::launch_gather_state(c->n, c->perm, spare, c->U[c->cur], c->stream));
+    c->probe_pending = speculative && method == FV_ORDER_CM;
+    return FV_OK;
+}
+
+// Wait for the confirming sweep of a speculative renumbering (its scratch
+// memory is free afterwards).  With `check`, compare its eccentricities with
+// the first sweeps' and, if some search would have moved, renumber again
+// without speculation: the labels then are exactly those of the sequential
+// search.  The state keeps its values (a step gives the same bits in any
+// cell order), so only the working order changes.
+fv_status settle(fv_ctx *c, bool check)
+{
+    if (!c->probe_pending)
+        return FV_OK;
+    c->probe_pending = false;
+    HIP_TRY(hipEventSynchronize(c->ev_probed));
+    if (!check)
+        return FV_OK;
+    std::vector<int4> st((size_t)c->n_seg);
+    std::vector<int32_t> pr((size_t)c->n_seg);
+    HIP_TRY(hipMemcpyAsync(st.data(), c->cm_state, st.size() * sizeof(int4),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(pr.data(), c->cm_probe, pr.size() * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    bool moved = false;
+    for (int32_t k = 0; k < c->n_seg; ++k)
+        moved = moved || (st[k].x > 0 && pr[k] > st[k].y);
+    if (!moved)
+        return FV_OK;
+    drop_graph(c);
+    if (fv_status s2 = renumber_now(c, FV_ORDER_CM, false))
+        return s2;
+    HIP_TRY(hipStreamSynchronize(c->stream));
     return FV_OK;
 }
 
@@ -487,6 +570,9 @@ fv_status upload(fv_ctx *c, int32_t n_seg, const int64_t *seg, const int32_t *nb
         return st;
     if (fv_status st = validate_segments(c->n, n_seg, seg, nbr))
         return st;
+    // the scratch memory is staged below: wait for a confirming sweep
+    if (fv_status st = settle(c, false))
+        return st;
     const size_t n = (size_t)c->n;
     c->mesh_ready = false;
     c->state_ready = false;
@@ -554,6 +640,8 @@ fv_status fv_upload_state(fv_ctx *c, const double *U)
         return fail(FV_ESTATE, "upload the mesh before the state");
     if (fv_status st = validate_state(c->n, U, c->gamma))
         return st;
+    if (fv_status st = settle(c, true))
+        return st;
     HIP_TRY(hipMemcpyAsync(c->scratch, U, (size_t)c->n * 4 * sizeof(double),
                            hipMemcpyHostToDevice, c->stream));
     HIP_TRY(fvk::launch_gather_state(c->n, c->perm, reinterpret_cast<const double4 *>(c->scratch),
@@ -589,24 +677,12 @@ fv_status fv_renumber(fv_ctx *c, int32_t method, int32_t *perm_out)
         return fail(FV_EINVAL, "unknown renumbering method %d", method);
     if (!c->mesh_ready)
         return fail(FV_ESTATE, "upload the mesh before renumbering");
-    // The state moves to the uploaded order in the spare buffer, then to the
-    // new order in the current one.
-    double4 *spare = c->U[c->cur ^ 1];
-    if (c->state_ready)
-        HIP_TRY(fvk::launch_gather_state(c->n, c->label, c->U[c->cur], spare, c->stream));
-    c->cm_passes = false;
-    if (method == FV_ORDER_IDENTITY) {
-        HIP_TRY(fvk::launch_iota(c->perm, c->n, c->stream));
-        HIP_TRY(fvk::launch_iota(c->label, c->n, c->stream));
-    } else {
-        if (fv_status st = cm_order(c))
-            return st;
-        c->cm_passes = true;
-    }
-    if (fv_status st = regather_geometry(c))
+    // a pending confirming sweep is only waited for: this renumbering replaces it
+    if (fv_status st = settle(c, false))
         return st;
-    if (c->state_ready)
-        HIP_TRY(fvk::launch_gather_state(c->n, c->perm, spare, c->U[c->cur], c->stream));
+    // without perm_out nothing waits for the confirming sweep (speculative)
+    if (fv_status st = renumber_now(c, method, method == FV_ORDER_CM && !perm_out))
+        return st;
     if (perm_out)
         HIP_TRY(hipMemcpyAsync(perm_out, c->perm, (size_t)c->n * sizeof(int32_t),
                                hipMemcpyDeviceToHost, c->stream));
@@ -673,6 +749,8 @@ fv_status fv_step_adjoint_grad(fv_ctx *c, const double *d_U, double *d_lambda, d
         return fail(FV_EINVAL, "gradient array must be 8-byte aligned");
     if (d_grad && !c->corr_on)
         return fail(FV_ESTATE, "no correction is set: there is no parameter gradient");
+    if (fv_status st = settle(c, true))
+        return st;
     // The adjoint runs on the working (renumbered) geometry, like the step:
     // U and lambda are gathered into the working order (the spare state
     // buffer and the scratch memory), and each cell's result is written back
@@ -749,9 +827,28 @@ fv_status fv_renumber_passes(fv_ctx *c, int32_t *passes)
         return fail(FV_EINVAL, "null passes array");
     if (!c->mesh_ready)
         return fail(FV_ESTATE, "upload the mesh first");
+    if (fv_status st = settle(c, true))
+        return st;
     if (!c->cm_passes)
         return fail(FV_ESTATE, "no Cuthill-McKee renumbering of this mesh yet");
     HIP_TRY(hipMemcpyAsync(passes, c->passes_dev, (size_t)c->n_seg * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return FV_OK;
+}
+
+fv_status fv_working_order(fv_ctx *c, int32_t *perm_out)
+{
+    g_last_error.clear();
+    if (fv_status st = check_ctx(c))
+        return st;
+    if (!perm_out)
+        return fail(FV_EINVAL, "null permutation array");
+    if (!c->mesh_ready)
+        return fail(FV_ESTATE, "upload the mesh first");
+    if (fv_status st = settle(c, true))
+        return st;
+    HIP_TRY(hipMemcpyAsync(perm_out, c->perm, (size_t)c->n * sizeof(int32_t),
                            hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return FV_OK;
@@ -766,6 +863,8 @@ fv_status fv_download_state(fv_ctx *c, double *U)
         return fail(FV_EINVAL, "null state");
     if (!c->state_ready)
         return fail(FV_ESTATE, "no state uploaded");
+    if (fv_status st = settle(c, true))
+        return st;
     double4 *stage = reinterpret_cast<double4 *>(c->scratch);
     HIP_TRY(fvk::launch_gather_state(c->n, c->label, c->U[c->cur], stage, c->stream));
     HIP_TRY(hipMemcpyAsync(U, stage, (size_t)c->n * 4 * sizeof(double), hipMemcpyDeviceToHost,
@@ -838,9 +937,16 @@ fv_status fv_destroy(fv_ctx *c)
     g_last_error.clear();
     if (!c)
         return fail(FV_EINVAL, "null context");
+    (void)settle(c, false);
     drop_graph(c);
     if (c->cap_stream)
         (void)hipStreamDestroy(c->cap_stream);
+    if (c->side)
+        (void)hipStreamDestroy(c->side);
+    if (c->ev_renamed)
+        (void)hipEventDestroy(c->ev_renamed);
+    if (c->ev_probed)
+        (void)hipEventDestroy(c->ev_probed);
     delete c;
     return FV_OK;
 }

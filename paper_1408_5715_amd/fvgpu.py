@@ -34,7 +34,7 @@ EXPORTS = (
     "fv_upload_state_device", "fv_renumber", "fv_step", "fv_step_batch", "fv_step_adjoint",
     "fv_step_adjoint_grad", "fv_set_correction", "fv_restrict", "fv_set_launch",
     "fv_renumber_passes", "fv_download_state", "fv_download_state_device", "fv_bytes_per_update",
-    "fv_check_state", "fv_destroy", "fv_last_error", "fv_step_static",
+    "fv_check_state", "fv_destroy", "fv_last_error", "fv_step_static", "fv_working_order",
 )
 
 
@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
         L.fv_upload_state.argtypes = [vp, vp]
         L.fv_upload_state_device.argtypes = [vp, vp]
         L.fv_renumber.argtypes = [vp, i32, vp]
+        L.fv_working_order.argtypes = [vp, vp]
         L.fv_step.argtypes = [vp, i32, dbl]
         L.fv_download_state.argtypes = [vp, vp]
         L.fv_download_state_device.argtypes = [vp, vp]
@@ -197,7 +198,15 @@ def fv_upload_state_device(ctx: int, d_U) -> None:
 
 
 def fv_renumber(ctx: int, method: int, perm_out: np.ndarray | None = None) -> None:
+    """Without perm_out, a Cuthill-McKee renumbering does not wait for the
+    root search's confirming sweep (see include/fvgpu.h)."""
     _check(lib().fv_renumber(ctx, int(method), _ptr(perm_out)))
+
+
+def fv_working_order(ctx: int, n: int) -> np.ndarray:
+    perm = np.empty(n, dtype=np.int32)
+    _check(lib().fv_working_order(ctx, _ptr(perm)))
+    return perm
 
 
 def fv_step(ctx: int, n_steps: int, dt: float) -> None:
@@ -278,6 +287,9 @@ class Solver:
 
     def set_launch(self, block: int = 256, grid: int = 0, use_graph: bool = False) -> None:
         fv_set_launch(self.ctx, block, grid, use_graph)
+
+    def working_order(self) -> np.ndarray:
+        return fv_working_order(self.ctx, self.n)
 
     def renumber_passes(self) -> np.ndarray:
         return fv_renumber_passes(self.ctx, self.n_meshes)
