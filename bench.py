@@ -155,18 +155,22 @@ def cpu_baseline(m, U0, dt, fv_steps: int, sample_steps: int) -> dict:
     }
 
 
-def hbm_resident_step(dev, N: int, fv_steps: int) -> dict:
-    """The step kernel on an N x N-quad mesh whose working set is far beyond
-    the 256 MB Infinity Cache (N = 2048: 8,388,608 cells, about 0.8 GB read
-    and written per step), renumbered: HIP events over fv_steps launches."""
+def hbm_resident_step(dev, N: int, fv_steps: int, snap_bits: int = 32) -> dict:
+    """The step kernel on an N x N-quad mesh, renumbered: HIP events over
+    fv_steps launches.  N = 2048 (8,388,608 cells, about 0.8 GB read and
+    written per step) puts the working set far beyond the 256 MB Infinity
+    Cache.  snap_bits > 32 gives a mesh whose normals are not multiples of
+    2^-32, so the step reads them as float64 (the layout of a general mesh
+    with exact vertex differences, 112 bytes per update)."""
     import torch
 
     import paper_1408_5715_amd as fv
     from fvgen import ic
     from fvgen.mesh import periodic_mesh, permute_mesh, random_permutation
 
-    log(f"HBM-resident case: generating the {N}x{N}-quad mesh")
-    m = permute_mesh(periodic_mesh(N, seed=1), random_permutation(2 * N * N, 2))
+    log(f"step case: generating the {N}x{N}-quad mesh (coordinates on a 2^-{snap_bits} grid)")
+    m = permute_mesh(periodic_mesh(N, seed=1, snap_bits=snap_bits),
+                     random_permutation(2 * N * N, 2))
     P = ic.bumps_primitive(m.centroid, seed=3)
     U0 = ic.to_conserved(P)
     dt = ic.cfl_dt(P, m.area, m.perimeter, 0.4)
@@ -192,8 +196,8 @@ def hbm_resident_step(dev, N: int, fv_steps: int) -> dict:
         s.close()
     achieved = ALG_BYTES_PER_UPDATE * m.n / t / 1e9
     return {
-        "workload": (f"periodic jittered {N}x{N}-quad mesh ({m.n} cells), renumbered on the GPU, "
-                     f"bump state; {fv_steps} steps"),
+        "workload": (f"periodic jittered {N}x{N}-quad mesh ({m.n} cells), coordinates on a "
+                     f"2^-{snap_bits} grid, renumbered on the GPU, bump state; {fv_steps} steps"),
         "cells": m.n,
         "step_us": t * 1e6,
         "cell_updates_per_s": m.n / t,
@@ -498,8 +502,10 @@ def main() -> int:
         del src, dst
 
     hbm = None
+    general = None
     if args.hbm_N > 0:
         hbm = hbm_resident_step(dev, args.hbm_N, 200)
+        general = hbm_resident_step(dev, N, 400, snap_bits=40)
         torch.cuda.empty_cache()
 
     trec = measured_traffic(n)
@@ -550,6 +556,9 @@ def main() -> int:
                      "hbm_resident times the same kernel on a mesh beyond it"),
         },
         "hbm_resident": hbm,
+        # the same kernel on the same mesh snapped to a finer grid, so that
+        # the two stored normals stay float64 (the general-mesh layout)
+        "general_layout": general,
         "cpu_baseline": cpu,
         "breakdown": {
             "renumber_and_upload_ms": float(np.median(renum_ms)),

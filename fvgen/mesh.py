@@ -48,13 +48,19 @@ class Mesh:
         return int(self.nbr.shape[0])
 
 
-def _snap(x: np.ndarray) -> np.ndarray:
-    s = float(2**SNAP_BITS)
+def _snap(x: np.ndarray, bits: int = SNAP_BITS) -> np.ndarray:
+    s = float(2**bits)
     return np.round(x * s) / s
 
 
-def periodic_mesh(N: int, L: float = 10.0, jitter: float = 0.2, seed: int = 1) -> Mesh:
-    """Build the N x N-quad periodic mesh (2 N^2 cells) in structured cell order."""
+def periodic_mesh(N: int, L: float = 10.0, jitter: float = 0.2, seed: int = 1,
+                  snap_bits: int = SNAP_BITS) -> Mesh:
+    """Build the N x N-quad periodic mesh (2 N^2 cells) in structured cell order.
+    snap_bits: coordinates are multiples of 2^-snap_bits (up to 45 keeps every
+    difference and periodic shift exact; above 32 the normals are no longer
+    multiples of 2^-32, as on a mesh that was not snapped to that grid)."""
+    if not 1 <= snap_bits <= 45:
+        raise ValueError("snap_bits must be in [1, 45]")
     if N < 2:
         raise ValueError("N must be >= 2 (N = 1 would give repeated neighbours)")
     h = L / N
@@ -69,8 +75,8 @@ def periodic_mesh(N: int, L: float = 10.0, jitter: float = 0.2, seed: int = 1) -
         Y = Y.copy()
         X[1:, 1:] += dx
         Y[1:, 1:] += dy
-    X = _snap(X)
-    Y = _snap(Y)
+    X = _snap(X, snap_bits)
+    Y = _snap(Y, snap_bits)
     Ls = float(L)
 
     # corner (di, dj) of quad (i, j) in unwrapped coordinates

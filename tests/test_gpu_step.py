@@ -377,3 +377,32 @@ def test_layout_variants(torch, closed, order):
     finally:
         s.close()
     assert np.all(rel_err(got, ref) <= TOL), rel_err(got, ref)
+
+
+@pytest.mark.slow
+def test_2048_mesh_beyond_the_cache(torch):
+    """The 2048 x 2048-quad mesh (8,388,608 cells) that bench.py times beyond
+    the Infinity Cache, in the same launch configuration (renumbered on the
+    GPU without waiting for the confirming sweep, one workgroup per tile):
+    10 steps against the oracle on every cell (the oracle's cell loop on the
+    host's cores, which gives its bits), and the layout is the compact one."""
+    import os
+
+    log("2048 mesh")
+    m, U0, dt = bumps_case(2048)
+    s = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        fv.fv_renumber(s.ctx, fv.FV_ORDER_CM)
+        assert s.bytes_per_update() == 96
+        fv.fv_upload_state_device(s.ctx, torch.tensor(U0, device="cuda"))
+        s.step(10, dt)
+        got = s.download_device().cpu().numpy()
+        assert int(s.renumber_passes()[0]) == 2
+    finally:
+        s.close()
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    log(f"2048 oracle 10 steps on {threads} threads")
+    ref, _ = oracle.default().step_threads(m.nbr, m.nrm, m.area, U0, dt, 10, threads)
+    err = rel_err(got, ref)
+    log(f"2048 mesh, 10 steps: {err}")
+    assert np.all(err <= TOL), err

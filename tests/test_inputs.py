@@ -131,3 +131,19 @@ def test_flow_features_scale_with_the_given_cell_size():
     rf = np.sum(w * Pf.rho[idx], 1)
     assert np.all(Pc.rho > 0) and np.all(Pc.p > 0) and np.all(Pf.p > 0)
     assert np.max(np.abs(rf - Pc.rho)) < 0.05 * np.max(np.abs(Pc.rho - 1.0))
+
+
+def test_finer_snapping_keeps_exactness_but_not_fixed_point():
+    """Coordinates on a 2^-40 grid: twin normals are still exact negations and
+    every cell's normals sum to zero (exact differences), but the normals are
+    no longer multiples of 2^-32, so the step reads them as float64."""
+    m = periodic_mesh(24, snap_bits=40)
+    assert np.all(m.nrm.sum(axis=1) == 0.0)
+    for i in range(m.n):
+        for f in range(3):
+            j = m.nbr[i, f]
+            assert any(np.all(m.nrm[j, g] == -m.nrm[i, f]) for g in range(3))
+    assert np.all(m.verts * 2.0**40 == np.round(m.verts * 2.0**40))
+    assert not np.all(m.nrm * 2.0**32 == np.round(m.nrm * 2.0**32))
+    with pytest.raises(ValueError):
+        periodic_mesh(8, snap_bits=46)
