@@ -16,7 +16,10 @@
  * applies the permutation on the device.
  *
  * Conventions for every entry point:
- *   - All work runs on the HIP stream given to fv_create, in issue order.
+ *   - All work runs on the HIP stream given to fv_create, in issue order,
+ *     except the confirming sweep of a Cuthill-McKee renumbering, which runs
+ *     on a second stream the context creates (default priority) and which
+ *     the calls that depend on it wait for (see fv_renumber).
  *   - Host arrays are read or written during the call only; the caller owns
  *     them.  Device memory is one arena the caller allocates and owns; the
  *     library never allocates or frees device memory.
