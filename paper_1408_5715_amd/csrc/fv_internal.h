@@ -93,20 +93,21 @@ hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *
 // n_seg + 1 offsets; no face crosses a segment), one workgroup per segment:
 // perm[label] = cell, label[cell] = label.  rec comes fresh from
 // launch_build_records; rec2 (n records), state and probe (n_seg entries
-// each), permA, permB, ordC and levA (n entries each) are scratch; passes[k]
-// receives the number of breadth-first passes of segment k.  The confirming
-// sweep of the pseudo-peripheral search runs on `side` between the events
-// `renamed` (recorded on s) and `probed` (recorded on side).  Not
-// speculative: s waits for it before the labels are final.  Speculative: the
-// labels assume the search does not move and s does not wait; the caller must
-// wait for `probed`, and if some probe[k] > state[k].y (the eccentricity
-// grew), renumber again without speculation.  Until `probed`, the scratch
-// arrays rec2, ordC and probe are in use on `side`.
+// each), permA and ordC (n entries each) are scratch; passes[k] receives the
+// number of breadth-first passes of segment k.  The confirming sweep of the
+// pseudo-peripheral search runs on `side` between the events `labelled`
+// (recorded on s) and `probed` (recorded on side).  Not speculative: s waits
+// for it before the labels are final.  Speculative: the labels assume the
+// search does not move and s does not wait; the caller must wait for
+// `probed`, and if some probe[k] > state[k].y (the eccentricity grew),
+// renumber again without speculation.  Until `probed`, `side` reads rec's
+// neighbour fields, state and the first components' labels in perm, and
+// writes rec2, ordC and probe.
 hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe, int32_t n,
-                              int32_t n_seg, const int64_t *seg, int32_t *permA, int32_t *permB,
-                              int32_t *ordC, int32_t *levA, int32_t *perm, int32_t *label,
-                              int32_t *passes, hipStream_t s, hipStream_t side,
-                              hipEvent_t renamed, hipEvent_t probed, bool speculative);
+                              int32_t n_seg, const int64_t *seg, int32_t *permA, int32_t *ordC,
+                              int32_t *perm, int32_t *label, int32_t *passes, hipStream_t s,
+                              hipStream_t side, hipEvent_t labelled, hipEvent_t probed,
+                              bool speculative);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_iota(int32_t *p, int32_t count, hipStream_t s);

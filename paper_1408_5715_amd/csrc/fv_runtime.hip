@@ -72,8 +72,8 @@ struct Layout {
         area = align_up(ld * 8);
         idx = align_up(ld * 4);
         // >= AoS normals (48 B), state (32 B), renumbering scratch (records,
-        // two orders, renamed records, level starts, the confirming sweep's
-        // order: 48 B)
+        // a second order, renamed records, the confirming sweep's order:
+        // 40 B)
         scratch = align_up(ld * 48);
         // segment offsets (int64), per-segment dt (double), per-segment pass
         // counts (int32), per-segment first-sweep results (int4) and
@@ -135,7 +135,7 @@ struct fv_ctx {
     float *corr_partial = nullptr;  // per-workgroup parameter gradients
     hipStream_t cap_stream = nullptr;  // private stream for graph capture
     hipStream_t side = nullptr;        // second stream of the renumbering (default priority)
-    hipEvent_t ev_renamed = nullptr;   // renamed graph ready (recorded on `stream`)
+    hipEvent_t ev_labelled = nullptr;  // first labelling pass done (recorded on `stream`)
     hipEvent_t ev_probed = nullptr;    // confirming sweep done (recorded on `side`)
     bool probe_pending = false;        // a speculative renumbering's confirming sweep is unchecked
     hipGraph_t graph = nullptr;
@@ -264,8 +264,8 @@ fv_status ensure_side(fv_ctx *c)
 {
     if (!c->side)
         HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-    if (!c->ev_renamed)
-        HIP_TRY(hipEventCreateWithFlags(&c->ev_renamed, hipEventDisableTiming));
+    if (!c->ev_labelled)
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_labelled, hipEventDisableTiming));
     if (!c->ev_probed)
         HIP_TRY(hipEventCreateWithFlags(&c->ev_probed, hipEventDisableTiming));
     return FV_OK;
@@ -275,25 +275,22 @@ fv_status ensure_side(fv_ctx *c)
 // c->perm / c->label, one workgroup per segment, all on the device (the
 // confirming sweep of the root search on the second stream; see
 // launch_cm_segments for `speculative`).  Scratch use (bytes per cell):
-// records 16, two orders 4 + 4, renamed records 16, level starts 4, the
-// confirming sweep's order 4 (ld is a multiple of 64, so every part stays
-// aligned).
+// records 16, a second order 4, renamed records 16, the confirming sweep's
+// order 4 (ld is a multiple of 64, so every part stays aligned).
 fv_status cm_order(fv_ctx *c, bool speculative)
 {
     const int32_t n = c->n;
     const size_t ld = (size_t)c->ld;
     int4 *rec = reinterpret_cast<int4 *>(c->scratch);
     int32_t *permA = reinterpret_cast<int32_t *>(rec + ld);
-    int32_t *permB = permA + ld;
-    int4 *rec2 = reinterpret_cast<int4 *>(permB + ld);
-    int32_t *levA = reinterpret_cast<int32_t *>(rec2 + ld);
-    int32_t *ordC = levA + ld;
+    int4 *rec2 = reinterpret_cast<int4 *>(permA + ld);
+    int32_t *ordC = reinterpret_cast<int32_t *>(rec2 + ld);
     if (fv_status st = ensure_side(c))
         return st;
     HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
     HIP_TRY(fvk::launch_cm_segments(rec, rec2, c->cm_state, c->cm_probe, n, c->n_seg, c->seg_dev,
-                                    permA, permB, ordC, levA, c->perm, c->label, c->passes_dev,
-                                    c->stream, c->side, c->ev_renamed, c->ev_probed, speculative));
+                                    permA, ordC, c->perm, c->label, c->passes_dev, c->stream,
+                                    c->side, c->ev_labelled, c->ev_probed, speculative));
     return FV_OK;
 }
 
@@ -943,8 +940,8 @@ fv_status fv_destroy(fv_ctx *c)
         (void)hipStreamDestroy(c->cap_stream);
     if (c->side)
         (void)hipStreamDestroy(c->side);
-    if (c->ev_renamed)
-        (void)hipEventDestroy(c->ev_renamed);
+    if (c->ev_labelled)
+        (void)hipEventDestroy(c->ev_labelled);
     if (c->ev_probed)
         (void)hipEventDestroy(c->ev_probed);
     delete c;
