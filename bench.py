@@ -209,9 +209,11 @@ def hbm_resident_step(dev, N: int, fv_steps: int, snap_bits: int = 32) -> dict:
     }
 
 
-def bench_batch(args, dev) -> int:
-    """The batched workload: renumber every mesh (one workgroup each, side by
-    side), tune the launch shape, then time the step over all meshes."""
+def batch_case(dev, fv_steps: int, warmup: int, reps: int) -> dict:
+    """The batched workload: renumber every mesh of the 64-mesh batch (one
+    workgroup each, side by side), tune the launch shape, then time fv_steps
+    steps over all meshes, reps times after warmup untimed runs, with the
+    tuned launch and with persistent workgroups replayed from one graph."""
     import numpy as np
     import torch
 
@@ -219,7 +221,6 @@ def bench_batch(args, dev) -> int:
     from fvgen.batch import batch_workload, concat
     from paper_1408_5715_amd import autotune
 
-    fv_steps = args.fv_steps if args.fv_steps != 1000 else 500
     log("generating the 64-mesh batch")
     parts, begin, sizes, Us, dts = batch_workload()
     nbr, nrm, area = concat(parts)
@@ -240,17 +241,20 @@ def bench_batch(args, dev) -> int:
     tuned = autotune.tune(s, dts, steps=10)
     log(f"launch: block {tuned['block']} grid {tuned['grid']} graph {tuned['graph']}"
         f"{' (cached)' if tuned.get('cached') else ''}")
-    times = []
-    for _ in range(args.warmup + args.steps):
-        s.upload_state(dU0)
-        a, b = ev(), ev()
-        a.record(s.stream)
-        s.step(fv_steps, dts)
-        b.record(s.stream)
-        torch.cuda.synchronize()
-        times.append(a.elapsed_time(b))
-    times = times[args.warmup:]
-    ms = float(np.median(times))
+
+    def timed() -> float:
+        times = []
+        for _ in range(warmup + reps):
+            s.upload_state(dU0)
+            a, b = ev(), ev()
+            a.record(s.stream)
+            s.step(fv_steps, dts)
+            b.record(s.stream)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        return float(np.median(times[warmup:]))
+
+    ms = timed()
     bpu = fv.fv_bytes_per_update(s.ctx)
     # the configuration's own launch form, beside the tuned one: persistent
     # workgroups (5 per CU) striding over the tiles, the whole step sequence
@@ -258,22 +262,35 @@ def bench_batch(args, dev) -> int:
     persistent = {"block": 256, "grid": 5 * torch.cuda.get_device_properties(dev).multi_processor_count,
                   "graph": True}
     s.set_launch(persistent["block"], persistent["grid"], persistent["graph"])
-    ptimes = []
-    for _ in range(args.warmup + args.steps):
-        s.upload_state(dU0)
-        a, b = ev(), ev()
-        a.record(s.stream)
-        s.step(fv_steps, dts)
-        b.record(s.stream)
-        torch.cuda.synchronize()
-        ptimes.append(a.elapsed_time(b))
-    pms = float(np.median(ptimes[args.warmup:]))
+    pms = timed()
     persistent.update({"step_us": pms * 1e3 / fv_steps,
                        "cell_updates_per_s": n * fv_steps / (pms * 1e-3)})
     s.close()
+    achieved = ALG_BYTES_PER_UPDATE * n * fv_steps / (ms * 1e-3) / 1e9
+    return {
+        "workload": (f"batch of {len(parts)} periodic jittered meshes "
+                     f"({int(sizes.min())}..{int(sizes.max())} quads per side, "
+                     f"{n} cells), {fv_steps} FP64 steps per run, per-mesh dt"),
+        "cells": n, "meshes": len(parts), "fv_steps": fv_steps, "ms": ms,
+        "step_us": ms * 1e3 / fv_steps,
+        "cell_updates_per_s": n * fv_steps / (ms * 1e-3),
+        "achieved": achieved, "frac": achieved / HBM_PEAK_GBS,
+        "layout_bytes_per_cell_update": bpu,
+        "layout_achieved": bpu * n * fv_steps / (ms * 1e-3) / 1e9,
+        "launch": {k: tuned[k] for k in ("block", "grid", "graph")},
+        "persistent_graph_launch": persistent,
+        "renumber_ms": renum_ms, "renumber_passes_max": int(passes.max()),
+    }
+
+
+def bench_batch(args, dev) -> int:
+    """The batched workload as its own line."""
+    fv_steps = args.fv_steps if args.fv_steps != 1000 else 500
+    c = batch_case(dev, fv_steps, args.warmup, args.steps)
+    ms = c["ms"]
     rec = {
         "metric": "cell-updates/s",
-        "value": n * fv_steps / (ms * 1e-3),
+        "value": c["cell_updates_per_s"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -284,21 +301,19 @@ def bench_batch(args, dev) -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": (f"batch of {len(parts)} periodic jittered meshes "
-                                f"({int(sizes.min())}..{int(sizes.max())} quads per side, "
-                                f"{n} cells), {fv_steps} FP64 steps per run, per-mesh dt"),
-                   "cells": n, "meshes": len(parts), "fv_steps": fv_steps},
+        "config": {"workload": c["workload"], "cells": c["cells"], "meshes": c["meshes"],
+                   "fv_steps": fv_steps},
         "roofline": {"bound": "hbm", "kernel": "fv_step_kernel",
-                     "achieved": ALG_BYTES_PER_UPDATE * n * fv_steps / (ms * 1e-3) / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ALG_BYTES_PER_UPDATE * n * fv_steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_cell_update": ALG_BYTES_PER_UPDATE,
-                     "layout_bytes_per_cell_update": bpu,
-                     "layout_achieved": bpu * n * fv_steps / (ms * 1e-3) / 1e9},
-        "launch": {k: tuned[k] for k in ("block", "grid", "graph")},
-        "persistent_graph_launch": persistent,
-        "breakdown": {"renumber_ms": renum_ms, "renumber_passes_max": int(passes.max()),
-                      "step_us": ms * 1e3 / fv_steps},
+                     "achieved": c["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": c["frac"], "traffic": None,
+                     "bytes_per_cell_update": ALG_BYTES_PER_UPDATE,
+                     "layout_bytes_per_cell_update": c["layout_bytes_per_cell_update"],
+                     "layout_achieved": c["layout_achieved"]},
+        "launch": c["launch"],
+        "persistent_graph_launch": c["persistent_graph_launch"],
+        "breakdown": {"renumber_ms": c["renumber_ms"],
+                      "renumber_passes_max": c["renumber_passes_max"],
+                      "step_us": c["step_us"]},
     }
     print(json.dumps(rec), flush=True)
     return 0
@@ -389,6 +404,8 @@ def main() -> int:
     ap.add_argument("--hbm-N", type=int, default=2048,
                     help="quads per side of the HBM-resident step timing (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true",
+                    help="leave the 64-mesh batch case out of the default line")
     ap.add_argument("--skip-random", action="store_true",
                     help="skip timing the step on the random (not renumbered) order")
     ap.add_argument("--workload", choices=("single", "batch", "learned"), default="single",
@@ -507,6 +524,10 @@ def main() -> int:
         hbm = hbm_resident_step(dev, args.hbm_N, 200)
         general = hbm_resident_step(dev, N, 400, snap_bits=40)
         torch.cuda.empty_cache()
+    batch = None
+    if not args.skip_batch:
+        batch = batch_case(dev, 500, 1, 3)
+        torch.cuda.empty_cache()
 
     trec = measured_traffic(n)
     traffic = None if trec is None else trec["fetch_bytes"] + trec["write_bytes"]
@@ -559,6 +580,8 @@ def main() -> int:
         # the same kernel on the same mesh snapped to a finer grid, so that
         # the two stored normals stay float64 (the general-mesh layout)
         "general_layout": general,
+        # the 64-mesh batch (20k..500k cells each, 11.9M in all), 500 steps
+        "batch": batch,
         "cpu_baseline": cpu,
         "breakdown": {
             "renumber_and_upload_ms": float(np.median(renum_ms)),

@@ -31,7 +31,7 @@ export PYTHONPATH="$ROOT${PYTHONPATH:+:$PYTHONPATH}"
 cd /tmp
 if [ "${1:-}" = "renumber" ]; then
     # one job of bench.py (renumbering + 20 steps) under two counter passes
-    JOB=(python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random --hbm-N 0)
+    JOB=(python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random --hbm-N 0 --skip-batch)
     echo "[profile] renumber: SQ counters" >&2
     timeout -s KILL 120 rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY \
         SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_INSTS_VALU SQ_INSTS_VMEM_RD -f csv \
@@ -68,18 +68,18 @@ if [ "${1:-}" = "learned" ]; then
 fi
 echo "[profile] kernel trace" >&2
 timeout -k 10 300 rocprofv3 --kernel-trace --stats -f csv -d "$OUT/prof_trace" -o trace -- \
-    python3 "$ROOT/bench.py" --steps 3 --warmup 1 --no-cpu-baseline --skip-random --hbm-N 0 \
+    python3 "$ROOT/bench.py" --steps 3 --warmup 1 --no-cpu-baseline --skip-random --hbm-N 0 --skip-batch \
     > "$OUT/prof_trace.log" 2>&1
 echo "[profile] FETCH_SIZE" >&2
 timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -f csv -d "$OUT/prof_fetch" -o fetch -- \
-    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random --hbm-N 0 \
+    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random --hbm-N 0 --skip-batch \
     --probe-copy > "$OUT/prof_fetch.log" 2>&1
 echo "[profile] WRITE_SIZE" >&2
 timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -f csv -d "$OUT/prof_write" -o write -- \
-    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random --hbm-N 0 \
+    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --skip-random --hbm-N 0 --skip-batch \
     --probe-copy > "$OUT/prof_write.log" 2>&1
 echo "[profile] L2 hits and misses (random order, then renumbered)" >&2
 timeout -s KILL 120 rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -f csv -d "$OUT/prof_l2" -o l2 -- \
-    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --hbm-N 0 \
+    python3 "$ROOT/bench.py" --steps 1 --warmup 0 --fv-steps 20 --no-cpu-baseline --hbm-N 0 --skip-batch \
     > "$OUT/prof_l2.log" 2>&1
 echo "[profile] done" >&2
