@@ -269,13 +269,13 @@ fv_status fv_set_launch(fv_ctx *ctx, int32_t block, int32_t grid, int32_t use_gr
 /*
  * Number of breadth-first passes (level structures of section 4's
  * renumbering, including the pseudo-peripheral search) each mesh took in the
- * last fv_renumber with FV_ORDER_CM.  The search's second sweep over a mesh's
- * first component runs on a copy of the graph renamed by the first sweep's
- * breadth-first order (same eccentricity, better memory locality); if the
- * eccentricity does not grow, the labels follow from the first sweep's
- * levels and the mesh counts 2 passes; if it grows, the search repeats that
- * sweep as a labelling pass on the uploaded graph, so such a mesh counts one
- * pass more than the sequential search takes.
+ * last fv_renumber with FV_ORDER_CM.  The search's first pass over a mesh's
+ * first component labels it from the lowest id; the second sweep runs on a
+ * copy of the graph renamed by those labels (same eccentricity, better
+ * memory locality).  If the eccentricity does not grow, the first pass's
+ * labels are the result and the mesh counts 2 passes; if it grows, the
+ * search repeats that sweep as a labelling pass on the uploaded graph, so
+ * such a mesh counts one pass more than the sequential search takes.
  *   passes  host int32 [n_meshes].  Synchronises the stream.
  * FV_ESTATE if no FV_ORDER_CM renumbering ran since the mesh was uploaded
  * (or the last renumbering was FV_ORDER_IDENTITY).
