@@ -85,43 +85,47 @@ hipError_t launch_adjoint_learned(int32_t n, int32_t ld, const double4 *U, const
                                   float *partial, double *grad, hipStream_t s);
 
 // ---- renumbering --------------------------------------------------------
-// rec[v] = (nb_0[v], nb_1[v], nb_2[v], -1): the graph with an empty label slot.
-hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *rec,
-                                hipStream_t s);
+// rec[v]: the graph nb (int32 [n][3], the uploaded order) as 16-byte
+// records for the renumbering passes, no cell visited yet.
+hipError_t launch_build_records(int32_t n, const int32_t *nb, int4 *rec, hipStream_t s);
 
 // Cuthill-McKee order of every segment [seg[k], seg[k+1]) (device array of
 // n_seg + 1 offsets; no face crosses a segment), one workgroup per segment:
 // perm[label] = cell, label[cell] = label.  rec comes fresh from
 // launch_build_records; rec2 (n records), state and probe (n_seg entries
 // each), permA and ordC (n entries each) are scratch; passes[k] receives the
-// number of breadth-first passes of segment k.  The confirming sweep of the
-// pseudo-peripheral search runs on `side` between the events `labelled`
-// (recorded on s) and `probed` (recorded on side).  Not speculative: s waits
-// for it before the labels are final.  Speculative: the labels assume the
-// search does not move and s does not wait; the caller must wait for
-// `probed`, and if some probe[k] > state[k].y (the eccentricity grew),
-// renumber again without speculation.  Until `probed`, `side` reads rec's
-// neighbour fields, state and the first components' labels in perm, and
-// writes rec2, ordC and probe.
+// number of breadth-first passes of segment k.  Not speculative: the
+// confirming sweep of the pseudo-peripheral search (launch_cm_confirm) runs
+// on `side` and s waits for it before the labels are final.  Speculative: the
+// labels assume the search does not move, and the caller must launch the
+// confirming sweep itself once s holds nothing more that touches rec, rec2,
+// ordC, perm or state, wait for `probed`, and, if some probe[k] > state[k].y
+// (the eccentricity grew), renumber again without speculation.
 hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe, int32_t n,
                               int32_t n_seg, const int64_t *seg, int32_t *permA, int32_t *ordC,
                               int32_t *perm, int32_t *label, int32_t *passes, hipStream_t s,
                               hipStream_t side, hipEvent_t labelled, hipEvent_t probed,
                               bool speculative);
 
+// The confirming sweep of each segment's first component on `side`, after
+// everything queued on s (event `labelled`), recorded as `probed`: the graph
+// renamed by the first labels into rec2 (ordC as its inverse), then the sweep
+// from the first pass's pick, whose eccentricity goes to probe[k].  Until
+// `probed`, side reads rec's neighbour fields, state and the first
+// components' labels in perm, and writes rec2, ordC and probe.
+hipError_t launch_cm_confirm(const int4 *rec, int4 *rec2, const int4 *state, int32_t *probe,
+                             int32_t n, int32_t n_seg, const int64_t *seg, int32_t *ordC,
+                             const int32_t *perm, hipStream_t s, hipStream_t side,
+                             hipEvent_t labelled, hipEvent_t probed);
+
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_iota(int32_t *p, int32_t count, hipStream_t s);
 
 // ---- permutation gathers --------------------------------------------------
-// AoS host layouts to the device structure-of-arrays layout.
-hipError_t launch_nb_aos_to_soa(int32_t n, int32_t ld, const int32_t *aos, int32_t *soa,
-                                hipStream_t s);
-hipError_t launch_nrm_aos_to_soa(int32_t n, int32_t ld, const double *aos, double *soa,
-                                 hipStream_t s);
-
-// Working-order geometry from the uploaded mesh: for new cell l with
-// v = perm[l]: nb_w[f][l] = label[nb_o[f][v]], nrm_w[k][l] = nrm_o[k][v],
-// inv_area_w[l] = 1 / area_o[v].
+// Working-order geometry from the uploaded mesh (nb_o int32 [n][3] and
+// nrm_o double [n][6] as uploaded, area_o double [n]): for new cell l with
+// v = perm[l]: nb_w[f][l] = label[nb_o[v][f]], nrm_w[k][l] = nrm_o[v][k],
+// inv_area_w[l] = 1 / area_o[v].  nrm_o must be 16-byte aligned.
 hipError_t launch_gather_geometry(int32_t n, int32_t ld, const int32_t *perm, const int32_t *label,
                                   const int32_t *nb_o, const double *nrm_o, const double *area_o,
                                   int32_t *nb_w, double *nrm_w, double *inv_area_w, hipStream_t s);

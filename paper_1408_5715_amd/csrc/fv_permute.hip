@@ -19,32 +19,10 @@ inline unsigned grid_for(int64_t count)
     return (unsigned)((count + kBlock - 1) / kBlock);
 }
 
-__global__ void nb_aos_to_soa_kernel(int32_t n, int32_t ld, const int32_t *__restrict__ aos,
-                                     int32_t *__restrict__ soa)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) {
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-            soa[f * ld + i] = aos[3 * i + f];
-    }
-}
-
-__global__ void nrm_aos_to_soa_kernel(int32_t n, int32_t ld, const double *__restrict__ aos,
-                                      double *__restrict__ soa)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            soa[k * ld + i] = aos[6 * (int64_t)i + k];
-    }
-}
-
 __global__ void gather_geometry_kernel(int32_t n, int32_t ld, const int32_t *__restrict__ perm,
                                        const int32_t *__restrict__ label,
                                        const int32_t *__restrict__ nb_o,
-                                       const double *__restrict__ nrm_o,
+                                       const double2 *__restrict__ nrm_o,
                                        const double *__restrict__ area_o,
                                        int32_t *__restrict__ nb_w, double *__restrict__ nrm_w,
                                        double *__restrict__ inv_area_w)
@@ -53,12 +31,17 @@ __global__ void gather_geometry_kernel(int32_t n, int32_t ld, const int32_t *__r
     if (l >= n)
         return;
     const int v = perm[l];
+    // the uploaded cell's neighbours (12 bytes) and normals (48 bytes) lie
+    // together, so the scattered read touches one or two lines of each
 #pragma unroll
     for (int f = 0; f < 3; ++f)
-        nb_w[f * ld + l] = label[nb_o[f * ld + v]];
+        nb_w[f * ld + l] = label[nb_o[3 * (int64_t)v + f]];
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
-        nrm_w[k * ld + l] = nrm_o[k * ld + v];
+    for (int f = 0; f < 3; ++f) {
+        const double2 q = nrm_o[3 * (int64_t)v + f];
+        nrm_w[(2 * f) * ld + l] = q.x;
+        nrm_w[(2 * f + 1) * ld + l] = q.y;
+    }
     inv_area_w[l] = 1.0 / area_o[v];
 }
 
@@ -136,28 +119,13 @@ hipError_t launch_restrict(int64_t n, int32_t k, int64_t n_src, const double4 *s
     return hipGetLastError();
 }
 
-hipError_t launch_nb_aos_to_soa(int32_t n, int32_t ld, const int32_t *aos, int32_t *soa,
-                                hipStream_t s)
-{
-    hipLaunchKernelGGL(nb_aos_to_soa_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, ld, aos,
-                       soa);
-    return hipGetLastError();
-}
-
-hipError_t launch_nrm_aos_to_soa(int32_t n, int32_t ld, const double *aos, double *soa,
-                                 hipStream_t s)
-{
-    hipLaunchKernelGGL(nrm_aos_to_soa_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, ld, aos,
-                       soa);
-    return hipGetLastError();
-}
-
 hipError_t launch_gather_geometry(int32_t n, int32_t ld, const int32_t *perm, const int32_t *label,
                                   const int32_t *nb_o, const double *nrm_o, const double *area_o,
                                   int32_t *nb_w, double *nrm_w, double *inv_area_w, hipStream_t s)
 {
     hipLaunchKernelGGL(gather_geometry_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, n, ld, perm,
-                       label, nb_o, nrm_o, area_o, nb_w, nrm_w, inv_area_w);
+                       label, nb_o, reinterpret_cast<const double2 *>(nrm_o), area_o, nb_w, nrm_w,
+                       inv_area_w);
     return hipGetLastError();
 }
 

@@ -689,14 +689,14 @@ __global__ void invert_kernel(int32_t n, const int32_t *__restrict__ perm,
         label[perm[l]] = l;
 }
 
-// rec[v]: the records of build_records_kernel, no cell visited yet.
-__global__ void build_records_kernel(int32_t n, int32_t ld, const int32_t *__restrict__ nb,
+// rec[v]: the records of the graph nb (int32 [n][3]), no cell visited yet.
+__global__ void build_records_kernel(int32_t n, const int32_t *__restrict__ nb,
                                      int4 *__restrict__ rec)
 {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n)
         return;
-    const int a = nb[v], b = nb[ld + v], c = nb[2 * ld + v];
+    const int a = nb[3 * v], b = nb[3 * v + 1], c = nb[3 * v + 2];
     const int4 r = make_int4(a == v ? ~a : a, (b == v || b == a) ? ~b : b,
                              (c == v || c == a || c == b) ? ~c : c, 0);
     rec[v] = make_int4(r.x, r.y, r.z, unvisited_mark(r));
@@ -718,28 +718,22 @@ __global__ void iota_kernel(int32_t *__restrict__ p, int32_t count)
 
 }  // namespace
 
-hipError_t launch_build_records(int32_t n, int32_t ld, const int32_t *nb, int4 *rec,
-                                hipStream_t s)
+hipError_t launch_build_records(int32_t n, const int32_t *nb, int4 *rec, hipStream_t s)
 {
-    hipLaunchKernelGGL(build_records_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ld, nb,
-                       rec);
+    hipLaunchKernelGGL(build_records_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, nb, rec);
     return hipGetLastError();
 }
 
-hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe, int32_t n,
-                              int32_t n_seg, const int64_t *seg, int32_t *permA, int32_t *ordC,
-                              int32_t *perm, int32_t *label, int32_t *passes, hipStream_t s,
-                              hipStream_t side, hipEvent_t labelled, hipEvent_t probed,
-                              bool speculative)
+hipError_t launch_cm_confirm(const int4 *rec, int4 *rec2, const int4 *state, int32_t *probe,
+                             int32_t n, int32_t n_seg, const int64_t *seg, int32_t *ordC,
+                             const int32_t *perm, hipStream_t s, hipStream_t side,
+                             hipEvent_t labelled, hipEvent_t probed)
 {
-    hipLaunchKernelGGL(cm_first_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, seg, perm,
-                       state);
-    hipError_t e = hipGetLastError();
+    // on the second stream, after everything queued on s so far; ordC serves
+    // as the inverse of the first labels until the probe writes its own
+    // order there
+    hipError_t e = hipEventRecord(labelled, s);
     if (e != hipSuccess)
-        return e;
-    // the confirming sweep on the second stream: ordC serves as the inverse
-    // of the first labels until the probe writes its own order there
-    if ((e = hipEventRecord(labelled, s)) != hipSuccess)
         return e;
     if ((e = hipStreamWaitEvent(side, labelled, 0)) != hipSuccess)
         return e;
@@ -755,10 +749,27 @@ hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe
                        probe);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    if ((e = hipEventRecord(probed, side)) != hipSuccess)
+    return hipEventRecord(probed, side);
+}
+
+hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe, int32_t n,
+                              int32_t n_seg, const int64_t *seg, int32_t *permA, int32_t *ordC,
+                              int32_t *perm, int32_t *label, int32_t *passes, hipStream_t s,
+                              hipStream_t side, hipEvent_t labelled, hipEvent_t probed,
+                              bool speculative)
+{
+    hipLaunchKernelGGL(cm_first_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, seg, perm,
+                       state);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
         return e;
-    if (!speculative && (e = hipStreamWaitEvent(s, probed, 0)) != hipSuccess)
-        return e;
+    if (!speculative) {
+        if ((e = launch_cm_confirm(rec, rec2, state, probe, n, n_seg, seg, ordC, perm, s, side,
+                                   labelled, probed)) != hipSuccess)
+            return e;
+        if ((e = hipStreamWaitEvent(s, probed, 0)) != hipSuccess)
+            return e;
+    }
     hipLaunchKernelGGL(cm_finish_kernel, dim3(n_seg), dim3(kCmThreads), 0, s, rec, seg, state,
                        probe, permA, perm, passes, (int32_t)speculative);
     if ((e = hipGetLastError()) != hipSuccess)

@@ -71,10 +71,10 @@ struct Layout {
         nrm = align_up(ld * 6 * 8);
         area = align_up(ld * 8);
         idx = align_up(ld * 4);
-        // >= AoS normals (48 B), state (32 B), renumbering scratch (records,
+        // >= a staged state (32 B) and the renumbering's scratch (records,
         // a second order, renamed records, the confirming sweep's order:
         // 40 B)
-        scratch = align_up(ld * 48);
+        scratch = align_up(ld * 40);
         // segment offsets (int64), per-segment dt (double), per-segment pass
         // counts (int32), per-segment first-sweep results (int4) and
         // second-sweep eccentricities (int32, padded to 8 bytes)
@@ -102,7 +102,7 @@ struct fv_ctx {
 
     double4 *U[2] = {nullptr, nullptr};
     int cur = 0;
-    int32_t *nb_o = nullptr;  // uploaded mesh, structure of arrays
+    int32_t *nb_o = nullptr;  // uploaded mesh as uploaded: int32 [n][3], double [n][6]
     double *nrm_o = nullptr;
     double *area_o = nullptr;
     int32_t *nb_w = nullptr;  // working (renumbered) order
@@ -271,26 +271,49 @@ fv_status ensure_side(fv_ctx *c)
     return FV_OK;
 }
 
+// The renumbering's scratch memory (bytes per cell): records 16, a second
+// label order 4, renamed records 16, the confirming sweep's order 4 (ld is a
+// multiple of 64, so every part stays aligned).
+struct CmScratch {
+    int4 *rec;
+    int32_t *permA;
+    int4 *rec2;
+    int32_t *ordC;
+    explicit CmScratch(const fv_ctx *c)
+    {
+        const size_t ld = (size_t)c->ld;
+        rec = reinterpret_cast<int4 *>(c->scratch);
+        permA = reinterpret_cast<int32_t *>(rec + ld);
+        rec2 = reinterpret_cast<int4 *>(permA + ld);
+        ordC = reinterpret_cast<int32_t *>(rec2 + ld);
+    }
+};
+
 // Cuthill-McKee labelling of every segment of the uploaded graph into
-// c->perm / c->label, one workgroup per segment, all on the device (the
-// confirming sweep of the root search on the second stream; see
-// launch_cm_segments for `speculative`).  Scratch use (bytes per cell):
-// records 16, a second order 4, renamed records 16, the confirming sweep's
-// order 4 (ld is a multiple of 64, so every part stays aligned).
+// c->perm / c->label, one workgroup per segment, all on the device (see
+// launch_cm_segments for `speculative`; the caller then launches the
+// confirming sweep with cm_confirm).
 fv_status cm_order(fv_ctx *c, bool speculative)
 {
-    const int32_t n = c->n;
-    const size_t ld = (size_t)c->ld;
-    int4 *rec = reinterpret_cast<int4 *>(c->scratch);
-    int32_t *permA = reinterpret_cast<int32_t *>(rec + ld);
-    int4 *rec2 = reinterpret_cast<int4 *>(permA + ld);
-    int32_t *ordC = reinterpret_cast<int32_t *>(rec2 + ld);
+    const CmScratch m(c);
     if (fv_status st = ensure_side(c))
         return st;
-    HIP_TRY(fvk::launch_build_records(n, c->ld, c->nb_o, rec, c->stream));
-    HIP_TRY(fvk::launch_cm_segments(rec, rec2, c->cm_state, c->cm_probe, n, c->n_seg, c->seg_dev,
-                                    permA, ordC, c->perm, c->label, c->passes_dev, c->stream,
-                                    c->side, c->ev_labelled, c->ev_probed, speculative));
+    HIP_TRY(fvk::launch_build_records(c->n, c->nb_o, m.rec, c->stream));
+    HIP_TRY(fvk::launch_cm_segments(m.rec, m.rec2, c->cm_state, c->cm_probe, c->n, c->n_seg,
+                                    c->seg_dev, m.permA, m.ordC, c->perm, c->label,
+                                    c->passes_dev, c->stream, c->side, c->ev_labelled,
+                                    c->ev_probed, speculative));
+    return FV_OK;
+}
+
+// The confirming sweep of a speculative renumbering, on the second stream
+// after everything queued so far.
+fv_status cm_confirm(fv_ctx *c)
+{
+    const CmScratch m(c);
+    HIP_TRY(fvk::launch_cm_confirm(m.rec, m.rec2, c->cm_state, c->cm_probe, c->n, c->n_seg,
+                                   c->seg_dev, m.ordC, c->perm, c->stream, c->side,
+                                   c->ev_labelled, c->ev_probed));
     return FV_OK;
 }
 
@@ -405,7 +428,13 @@ fv_status renumber_now(fv_ctx *c, int32_t method, bool speculative)
         return st;
     if (c->state_ready)
         HIP_TRY(fvk::launch_gather_state(c->n, c->perm, spare, c->U[c->cur], c->stream));
-    c->probe_pending = speculative && method == FV_ORDER_CM;
+    if (speculative && method == FV_ORDER_CM) {
+        // after the gathers, so that its scattered loads do not compete with
+        // theirs on the critical path
+        if (fv_status st = cm_confirm(c))
+            return st;
+        c->probe_pending = true;
+    }
     return FV_OK;
 }
 
@@ -567,7 +596,8 @@ fv_status upload(fv_ctx *c, int32_t n_seg, const int64_t *seg, const int32_t *nb
         return st;
     if (fv_status st = validate_segments(c->n, n_seg, seg, nbr))
         return st;
-    // the scratch memory is staged below: wait for a confirming sweep
+    // perm and the renumbering's scratch memory change below: wait for a
+    // confirming sweep that may still read them
     if (fv_status st = settle(c, false))
         return st;
     const size_t n = (size_t)c->n;
@@ -581,14 +611,10 @@ fv_status upload(fv_ctx *c, int32_t n_seg, const int64_t *seg, const int32_t *nb
     c->seg_host.assign(seg, seg + n_seg + 1);
     HIP_TRY(hipMemcpyAsync(c->seg_dev, c->seg_host.data(), (n_seg + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->scratch, nbr, n * 3 * sizeof(int32_t), hipMemcpyHostToDevice,
+    HIP_TRY(hipMemcpyAsync(c->nb_o, nbr, n * 3 * sizeof(int32_t), hipMemcpyHostToDevice,
                            c->stream));
-    HIP_TRY(fvk::launch_nb_aos_to_soa(c->n, c->ld, reinterpret_cast<int32_t *>(c->scratch),
-                                      c->nb_o, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->scratch, nrm, n * 6 * sizeof(double), hipMemcpyHostToDevice,
+    HIP_TRY(hipMemcpyAsync(c->nrm_o, nrm, n * 6 * sizeof(double), hipMemcpyHostToDevice,
                            c->stream));
-    HIP_TRY(fvk::launch_nrm_aos_to_soa(c->n, c->ld, reinterpret_cast<double *>(c->scratch),
-                                       c->nrm_o, c->stream));
     HIP_TRY(hipMemcpyAsync(c->area_o, area, n * sizeof(double), hipMemcpyHostToDevice,
                            c->stream));
     HIP_TRY(fvk::launch_iota(c->perm, c->n, c->stream));
