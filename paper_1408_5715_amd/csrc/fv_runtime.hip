@@ -138,6 +138,8 @@ struct fv_ctx {
     hipEvent_t ev_labelled = nullptr;  // first labelling pass done (recorded on `stream`)
     hipEvent_t ev_probed = nullptr;    // confirming sweep done (recorded on `side`)
     bool probe_pending = false;        // a speculative renumbering's confirming sweep is unchecked
+    hipEvent_t ev_sync = nullptr;      // polled by wait_stream
+    int32_t *host_flag = nullptr;      // pinned host word for device flags
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     long long graph_key[6] = {-1, -1, -1, -1, -1, -1};
@@ -239,6 +241,22 @@ bool normals_closed(int64_t n, const double *nrm)
     return true;
 }
 
+// Wait for everything queued on the context's stream by polling an event.
+// The host then resumes within microseconds of the device, where a blocking
+// wait that follows a long renumbering can add a wake-up delay of the order
+// of 100 us, during which the device has nothing queued.
+fv_status wait_stream(fv_ctx *c)
+{
+    if (!c->ev_sync)
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(c->ev_sync, c->stream));
+    hipError_t e;
+    while ((e = hipEventQuery(c->ev_sync)) == hipErrorNotReady) {
+    }
+    HIP_TRY(e);
+    return FV_OK;
+}
+
 // Rebuild the working geometry for the current perm/label, and its 16-bit
 // neighbour offsets.  Synchronises the stream.
 fv_status regather_geometry(fv_ctx *c)
@@ -248,13 +266,18 @@ fv_status regather_geometry(fv_ctx *c)
     int32_t *dflag = reinterpret_cast<int32_t *>(c->small + 192);
     HIP_TRY(fvk::launch_fill_i32(dflag, 0, 1, c->stream));
     HIP_TRY(fvk::launch_narrow_offsets(c->n, c->ld, c->nb_w, c->nb16_w, dflag, c->stream));
-    int32_t too_far = 1;
-    HIP_TRY(hipMemcpyAsync(&too_far, dflag, sizeof(too_far), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    c->narrow = too_far == 0;
     if (c->fixed) {
         HIP_TRY(fvk::launch_fixed_normals(c->n, c->ld, c->nrm_w, c->nfx_w, c->stream));
     }
+    if (!c->host_flag)
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&c->host_flag), sizeof(int32_t),
+                              hipHostMallocDefault));
+    *c->host_flag = 1;
+    HIP_TRY(hipMemcpyAsync(c->host_flag, dflag, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           c->stream));
+    if (fv_status st = wait_stream(c))
+        return st;
+    c->narrow = *c->host_flag == 0;
     c->coef_dt.clear();
     return FV_OK;
 }
@@ -330,7 +353,8 @@ fv_status ensure_coef(fv_ctx *c, const double *dt)
     HIP_TRY(fvk::launch_coef(c->n, c->n_seg, c->seg_dev, c->dt_dev, c->inv_area_w, c->coef,
                              c->stream));
     // the host array of dt values is read by the copy; keep it alive until then
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (fv_status st = wait_stream(c))
+        return st;
     c->coef_dt.assign(dt, dt + c->n_seg);
     return FV_OK;
 }
@@ -405,16 +429,21 @@ fv_status run_steps(fv_ctx *c, int32_t n_steps)
 }
 
 // A renumbering of the mesh into c->perm / c->label and the working
-// geometry; the state, if any, follows into the new order.  The state moves
-// to the uploaded order in the spare buffer, then to the new order in the
-// current one.  Speculative (Cuthill-McKee only): the labels assume that no
+// geometry; the state, if any, follows into the new order in one gather
+// through the old and the new order, into the spare buffer, which becomes
+// the current one.  Speculative (Cuthill-McKee only): the labels assume that no
 // pseudo-peripheral search moves beyond its first candidate, and the
 // confirming sweep is left running on the second stream (see settle).
 fv_status renumber_now(fv_ctx *c, int32_t method, bool speculative)
 {
-    double4 *spare = c->U[c->cur ^ 1];
-    if (c->state_ready)
-        HIP_TRY(fvk::launch_gather_state(c->n, c->label, c->U[c->cur], spare, c->stream));
+    // the old inverse order, for the state, in the coef array (which the new
+    // geometry invalidates anyway)
+    int32_t *old_label = reinterpret_cast<int32_t *>(c->coef);
+    if (c->state_ready) {
+        c->coef_dt.clear();
+        HIP_TRY(hipMemcpyAsync(old_label, c->label, (size_t)c->n * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, c->stream));
+    }
     c->cm_passes = false;
     if (method == FV_ORDER_IDENTITY) {
         HIP_TRY(fvk::launch_iota(c->perm, c->n, c->stream));
@@ -426,8 +455,12 @@ fv_status renumber_now(fv_ctx *c, int32_t method, bool speculative)
     }
     if (fv_status st = regather_geometry(c))
         return st;
-    if (c->state_ready)
-        HIP_TRY(fvk::launch_gather_state(c->n, c->perm, spare, c->U[c->cur], c->stream));
+    if (c->state_ready) {
+        // new cell l is uploaded cell perm[l], which sat at old_label[perm[l]]
+        HIP_TRY(fvk::launch_gather_state2(c->n, c->perm, old_label, c->U[c->cur],
+                                          c->U[c->cur ^ 1], c->stream));
+        c->cur ^= 1;
+    }
     if (speculative && method == FV_ORDER_CM) {
         // after the gathers, so that its scattered loads do not compete with
         // theirs on the critical path
@@ -970,6 +1003,10 @@ fv_status fv_destroy(fv_ctx *c)
         (void)hipEventDestroy(c->ev_labelled);
     if (c->ev_probed)
         (void)hipEventDestroy(c->ev_probed);
+    if (c->ev_sync)
+        (void)hipEventDestroy(c->ev_sync);
+    if (c->host_flag)
+        (void)hipHostFree(c->host_flag);
     delete c;
     return FV_OK;
 }

@@ -135,10 +135,17 @@ def test_every_cell_written(torch):
     s = fv.Solver(m.nbr, m.nrm, m.area)
     try:
         s.upload_state(U0)
-        s.renumber(fv.FV_ORDER_CM)
+        perm = s.renumber(fv.FV_ORDER_CM)
         ld = (m.n + 63) // 64 * 64
-        # the second state buffer follows the first (32 bytes per cell)
-        s.arena[ld * 32: ld * 32 + m.n * 32].fill_(0xFF)
+        # the arena starts with the two state buffers (32 bytes per cell
+        # each); the one holding the state in the working order is the
+        # step's input, the other its output
+        work = np.ascontiguousarray(U0[perm]).view(np.uint8).reshape(-1)
+        first = s.arena[: m.n * 32].cpu().numpy()
+        out = 1 if np.array_equal(first, work) else 0
+        if out == 0:
+            assert np.array_equal(s.arena[ld * 32: ld * 32 + m.n * 32].cpu().numpy(), work)
+        s.arena[out * ld * 32: out * ld * 32 + m.n * 32].fill_(0xFF)
         torch.cuda.synchronize()
         s.step(1, dt)
         got = s.download()
