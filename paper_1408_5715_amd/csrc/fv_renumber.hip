@@ -187,12 +187,13 @@ __device__ __forceinline__ unsigned set_hash(int c)
     return ((unsigned)c * 0x9E3779B1u) >> 19;  // 13 bits
 }
 
-// Insert c into the set; true if this call inserted it (claims c).  At most
-// one sweep's new cells live in the set, fewer than kHashSlots, so an empty
-// slot is always reached; the loop is bounded by the table size.
-__device__ __forceinline__ bool claim(unsigned *set, int c)
+// Insert c into the set, probing from slot h on; true if this call inserted
+// it (claims c).  At most one sweep's new cells live in the set, fewer than
+// kHashSlots, so an empty slot is always reached; the loop is bounded by the
+// table size.  The sweeps issue every proposal's first probe at once and come
+// here only after a collision.
+__device__ __forceinline__ bool claim_from(unsigned *set, int c, unsigned h)
 {
-    unsigned h = set_hash(c);
     for (int probe = 0; probe < kHashSlots; ++probe) {
         const unsigned old = atomicCAS(set + h, kHashEmpty, (unsigned)c);
         if (old == kHashEmpty)
@@ -204,13 +205,13 @@ __device__ __forceinline__ bool claim(unsigned *set, int c)
     return false;
 }
 
-// Record the proposal of c by frontier position pos; returns c's slot (the
-// smallest proposing position sits in its low half once every proposal of
-// the sweep is in).  Bounded like claim.
-__device__ __forceinline__ int propose(unsigned long long *set, int c, int pos)
+// Record the proposal of c by frontier position pos, probing from slot h on;
+// returns c's slot (the smallest proposing position sits in its low half
+// once every proposal of the sweep is in).  Bounded like claim_from, and like
+// it reached only after a collision.
+__device__ __forceinline__ int propose_from(unsigned long long *set, int c, int pos, unsigned h)
 {
     const unsigned long long val = (unsigned long long)(unsigned)c << 32 | (unsigned)pos;
-    unsigned h = set_hash(c);
     for (int probe = 0; probe < kHashSlots; ++probe) {
         const unsigned long long old = atomicCAS(set + h, kPairEmpty, val);
         if (old == kPairEmpty)
@@ -287,20 +288,62 @@ __device__ __forceinline__ int bfs_sweep(int4 *__restrict__ graph, int32_t *__re
                     rw[k][f] = gv[ww];
             }
         }
+        // every proposal's first probe at once (one compare-and-swap each,
+        // all in flight together), then the rare collisions one by one
+        typedef typename SetSlot<kLabel>::T Slot;
+        const Slot empty = kLabel ? (Slot)kPairEmpty : (Slot)kHashEmpty;
+        bool fresh[P][3];
+        unsigned h0[P][3];
+        Slot old[P][3];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            won[k] = 0;
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
                 i4v r = rw[k][f];
                 asm volatile("" : "+v"(r));
                 rw[k][f] = r;
-                const bool fresh = cand[k][f] && r[3] < 0;
+                fresh[k][f] = cand[k][f] && r[3] < 0;
+                h0[k][f] = set_hash(w[k][f]);
+                Slot val;
+                if constexpr (kLabel)
+                    val = (Slot)(unsigned)w[k][f] << 32 | (unsigned)(first + k);
+                else
+                    val = (Slot)(unsigned)w[k][f];
+                old[k][f] = empty;
+                if (fresh[k][f])
+                    old[k][f] = atomicCAS(lds.set + h0[k][f], empty, val);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            won[k] = 0;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const int c = w[k][f];
+                const Slot o = old[k][f];
                 if constexpr (kLabel) {
-                    slot[k][f] = fresh ? propose(lds.set, w[k][f], first + k) : -1;
+                    int sl = -1;
+                    if (fresh[k][f]) {
+                        const unsigned h1 = (h0[k][f] + 1) & (kHashSlots - 1);
+                        if (o == empty) {
+                            sl = (int)h0[k][f];
+                        } else if ((unsigned)(o >> 32) == (unsigned)c) {
+                            sl = (int)h0[k][f];
+                            if ((unsigned)o > (unsigned)(first + k))
+                                atomicMin(lds.set + sl,
+                                          (Slot)(unsigned)c << 32 | (unsigned)(first + k));
+                        } else {
+                            sl = propose_from(lds.set, c, first + k, h1);
+                        }
+                    }
+                    slot[k][f] = sl;
                 } else {
-                    if (fresh && claim(lds.set, w[k][f]))
-                        won[k] |= 1u << f;
+                    if (fresh[k][f]) {
+                        const unsigned h1 = (h0[k][f] + 1) & (kHashSlots - 1);
+                        const bool mine = o == empty || (o != (Slot)(unsigned)c &&
+                                                         claim_from(lds.set, c, h1));
+                        won[k] |= (unsigned)mine << f;
+                    }
                 }
             }
         }
