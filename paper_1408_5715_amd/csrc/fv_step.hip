@@ -109,8 +109,21 @@ __device__ __forceinline__ double from_fixed(int k)
     return k == INT32_MIN ? -0.0 : (double)k * 0x1p-32;
 }
 
+// Per-cell arrays read once per step (offsets, fixed-point normals, dt/V),
+// with kStream as non-temporal loads: on a mesh whose working set exceeds
+// the Infinity Cache they would only displace the states that the
+// neighbour gathers reuse.
+template <bool kStream, typename T>
+__device__ __forceinline__ T read_once(const T *p)
+{
+    if constexpr (kStream)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
 // Update of one cell i (the body of the step).
-template <bool kNarrow, bool kClosed, bool kFixed>
+template <bool kNarrow, bool kClosed, bool kFixed, bool kStream>
 __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__restrict__ U,
                                             double4 *__restrict__ Un,
                                             const int32_t *__restrict__ nb,
@@ -121,7 +134,12 @@ __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__
 {
     int js[3];
     if constexpr (kNarrow) {
-        const short4 o = nb16[i];
+        short4 o;
+        {
+            // the four 16-bit offsets as one 8-byte word
+            const long long q = read_once<kStream>(reinterpret_cast<const long long *>(nb16) + i);
+            o = *reinterpret_cast<const short4 *>(&q);
+        }
         js[0] = i + o.x;
         js[1] = i + o.y;
         js[2] = i + o.z;
@@ -132,7 +150,9 @@ __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__
     }
     double nxs[3], nys[3];
     if constexpr (kFixed) {
-        const int4 q = nfx[i];
+        const int *qp = reinterpret_cast<const int *>(nfx) + 4 * (int64_t)i;
+        const int4 q = make_int4(read_once<kStream>(qp), read_once<kStream>(qp + 1),
+                                 read_once<kStream>(qp + 2), read_once<kStream>(qp + 3));
         nxs[0] = from_fixed(q.x);
         nys[0] = from_fixed(q.y);
         nxs[1] = from_fixed(q.z);
@@ -184,7 +204,7 @@ __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__
     }
 
     // coef = dt / V_T, formed as dt * (1 / V_T) by coef_kernel
-    const double k = coef[i];
+    const double k = read_once<kStream>(coef + i);
     double4 out;
     out.x = Ui.x - k * a0;
     out.y = Ui.y - k * a1;
@@ -197,7 +217,7 @@ __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__
 // remapped so that each XCD takes one contiguous range of tiles; with a
 // persistent grid of fewer workgroups, the tiles are split into one
 // contiguous range per XCD and the workgroups of each XCD stride through it.
-template <int kBlock, bool kNarrow, bool kClosed, bool kFixed>
+template <int kBlock, bool kNarrow, bool kClosed, bool kFixed, bool kStream>
 __global__ __launch_bounds__(kBlock) void fv_step_kernel(
     int32_t n, int32_t ld, const double4 *__restrict__ U, double4 *__restrict__ Un,
     const int32_t *__restrict__ nb, const short4 *__restrict__ nb16,
@@ -210,7 +230,8 @@ __global__ __launch_bounds__(kBlock) void fv_step_kernel(
         const int t = xcd_contiguous_block(b, G);
         const int i = t * kBlock + threadIdx.x;
         if (t < tiles && i < n)
-            update_cell<kNarrow, kClosed, kFixed>(i, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma);
+            update_cell<kNarrow, kClosed, kFixed, kStream>(i, ld, U, Un, nb, nb16, nrm, nfx, coef,
+                                                           gamma);
         return;
     }
     const int X = G < kXcds ? G : kXcds;  // XCDs that hold workgroups
@@ -220,7 +241,8 @@ __global__ __launch_bounds__(kBlock) void fv_step_kernel(
     for (int t = t0 + k; t < t1; t += Px) {
         const int i = t * kBlock + threadIdx.x;
         if (i < n)
-            update_cell<kNarrow, kClosed, kFixed>(i, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma);
+            update_cell<kNarrow, kClosed, kFixed, kStream>(i, ld, U, Un, nb, nb16, nrm, nfx, coef,
+                                                           gamma);
     }
 }
 
@@ -244,14 +266,20 @@ __global__ void coef_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict_
     coef[i] = dt[lo] * inv_area[i];
 }
 
-template <int kBlock, bool kNarrow, bool kClosed, bool kFixed>
+template <int kBlock, bool kNarrow, bool kClosed, bool kFixed, bool kStream = false>
 void launch_variant(int G, int32_t n, int32_t ld, const double4 *U, double4 *Un,
                     const int32_t *nb, const short4 *nb16, const double *nrm, const int4 *nfx,
                     const double *coef, double gamma, hipStream_t s)
 {
-    hipLaunchKernelGGL((fv_step_kernel<kBlock, kNarrow, kClosed, kFixed>), dim3(G), dim3(kBlock),
-                       0, s, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma);
+    hipLaunchKernelGGL((fv_step_kernel<kBlock, kNarrow, kClosed, kFixed, kStream>), dim3(G),
+                       dim3(kBlock), 0, s, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma);
 }
+
+// Bytes of the compact layout's working set per cell (two states, offsets,
+// fixed-point normals, dt/V) and the Infinity Cache of MI355X: a larger
+// working set streams the per-cell arrays past it.
+constexpr int64_t kCompactBytes = 2 * 32 + 8 + 16 + 8;
+constexpr int64_t kInfinityCache = int64_t(256) << 20;
 
 template <int kBlock>
 hipError_t launch_step_block(int32_t n, int32_t ld, const double4 *U, double4 *Un,
@@ -262,7 +290,10 @@ hipError_t launch_step_block(int32_t n, int32_t ld, const double4 *U, double4 *U
     const int tiles = (n + kBlock - 1) / kBlock;
     const int G = (grid <= 0 || grid > tiles) ? tiles : grid;
     fixed = fixed && closed;
-    if (narrow && fixed)
+    if (narrow && fixed && (int64_t)n * kCompactBytes > kInfinityCache)
+        launch_variant<kBlock, true, true, true, true>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef,
+                                                        gamma, s);
+    else if (narrow && fixed)
         launch_variant<kBlock, true, true, true>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, s);
     else if (fixed)
         launch_variant<kBlock, false, true, true>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, s);
