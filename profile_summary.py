@@ -203,7 +203,9 @@ def main_renumber() -> int:
     the CUs (one CU for a renumbering kernel, all 256 for the step)."""
     sq = per_dispatch(os.path.join(OUT, "rprof_sq", "sq_counter_collection.csv"))
     mem = per_dispatch(os.path.join(OUT, "rprof_mem", "mem_counter_collection.csv"))
-    step = "void fv_step_kernel<256, true, true, true>"
+    # the compact step (renumbered order, 16-bit offsets, fixed-point normals)
+    step = next((k for k in sq if k.startswith("void fv_step_kernel<256, true, true, true")),
+                "void fv_step_kernel<256, true, true, true, false>")
     # (kernel, CUs it runs on, levels it walks): the labelling pass and the
     # confirming sweep run on one CU each
     rows = [("cm_first_kernel", 1, 1366), ("cm_invert_kernel", 256, 0),
