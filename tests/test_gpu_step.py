@@ -413,3 +413,31 @@ def test_2048_mesh_beyond_the_cache(torch):
     err = rel_err(got, ref)
     log(f"2048 mesh, 10 steps: {err}")
     assert np.all(err <= TOL), err
+
+
+@pytest.mark.slow
+def test_streaming_step_equals_cached_step_bitwise(torch):
+    """A mesh whose compact working set (96 B per cell) exceeds the 256 MB
+    Infinity Cache (1200 x 1200 quads, 2,880,000 cells: 276 MB) takes the
+    step variant with non-temporal reads of its per-cell arrays once
+    renumbered; on the uploaded (random) order it takes the 32-bit index
+    variant without them.  A step gives the same bits in any cell order, so
+    the two runs must agree bit for bit."""
+    log("streaming step 1200")
+    m, U0, dt = bumps_case(1200)
+    assert m.n * 96 > 256 << 20
+    a = fv.Solver(m.nbr, m.nrm, m.area)
+    b = fv.Solver(m.nbr, m.nrm, m.area)
+    try:
+        a.upload_state(U0)
+        a.renumber(fv.FV_ORDER_CM)
+        assert a.bytes_per_update() == 96
+        a.step(5, dt)
+        got = a.download()
+        b.upload_state(U0)
+        b.step(5, dt)
+        ref = b.download()
+    finally:
+        a.close()
+        b.close()
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
