@@ -129,7 +129,7 @@ struct BfsResult {
 //
 // A pass walks the levels of the root's component one sweep at a time.  A
 // frontier cell fetches the records of its neighbours not known to be
-// visited; the record's fourth field marks a visited cell (-1 while
+// visited; the record's fourth field marks a visited cell (negative while
 // unvisited), so the same load that brings a cell's neighbour list also says
 // whether it is new.  A new cell proposed by several frontier cells of one
 // sweep is resolved in an LDS hash set keyed by the cell:
