@@ -23,7 +23,7 @@
 // loop on the same block-uniform condition (an empty next level).
 //
 // The graph is read as 16-byte records: three neighbours and the cell's
-// mark (-1 while unvisited), so one cache-line fetch answers both "is w
+// mark (negative while unvisited), so one cache-line fetch answers both "is w
 // visited" and "who are w's neighbours".  Frontier cells carry their
 // neighbour lists in LDS (fetched when they were discovered), their
 // discoverer marked as visited; its record is not fetched again.  One CU
@@ -417,8 +417,8 @@ __device__ __forceinline__ int bfs_sweep(int4 *__restrict__ graph, int32_t *__re
 }
 
 // Breadth-first pass over the component of `root` in `graph` (records
-// (nb_0, nb_1, nb_2, mark), mark -1 for every cell of the component on
-// entry).  ord[base + p] receives the p-th cell reached (levels in order).
+// (nb_0, nb_1, nb_2, mark), the mark negative for every cell of the
+// component on entry).  ord[base + p] receives the p-th cell reached (levels in order).
 // With kLabel the order is the Cuthill-McKee labelling from the root, labels
 // from base, and every record's mark becomes its cell's label; without, the
 // marks are levels and the order within a level is arbitrary.  Called by all
