@@ -187,22 +187,22 @@ __device__ __forceinline__ unsigned set_hash(int c)
     return ((unsigned)c * 0x9E3779B1u) >> 19;  // 13 bits
 }
 
-// Insert c into the set, probing from slot h on; true if this call inserted
-// it (claims c).  At most one sweep's new cells live in the set, fewer than
-// kHashSlots, so an empty slot is always reached; the loop is bounded by the
-// table size.  The sweeps issue every proposal's first probe at once and come
-// here only after a collision.
-__device__ __forceinline__ bool claim_from(unsigned *set, int c, unsigned h)
+// Insert c into the set, probing from slot h on; the slot if this call
+// inserted it (claims c), else -1.  At most one sweep's new cells live in the
+// set, fewer than kHashSlots, so an empty slot is always reached; the loop is
+// bounded by the table size.  The sweeps issue every proposal's first probe
+// at once and come here only after a collision.
+__device__ __forceinline__ int claim_from(unsigned *set, int c, unsigned h)
 {
     for (int probe = 0; probe < kHashSlots; ++probe) {
         const unsigned old = atomicCAS(set + h, kHashEmpty, (unsigned)c);
         if (old == kHashEmpty)
-            return true;
+            return (int)h;
         if (old == (unsigned)c)
-            return false;
+            return -1;
         h = (h + 1) & (kHashSlots - 1);
     }
-    return false;
+    return -1;
 }
 
 // Record the proposal of c by frontier position pos, probing from slot h on;
@@ -246,7 +246,7 @@ __device__ __forceinline__ int bfs_sweep(int4 *__restrict__ graph, int32_t *__re
 
     int v[P], w[P][3];
     i4v rw[P][3];
-    int slot[P][3];  // with labels: the slot of each proposal, -1 for none
+    int slot[P][3];  // the proposal's slot (with labels) or the claimed slot, -1 for none
     unsigned won[P];  // bit f: w[k][f] is new and joins through this thread
     if (wave_busy) {
         bool ok[P];
@@ -338,12 +338,16 @@ __device__ __forceinline__ int bfs_sweep(int4 *__restrict__ graph, int32_t *__re
                     }
                     slot[k][f] = sl;
                 } else {
+                    int sl = -1;
                     if (fresh[k][f]) {
                         const unsigned h1 = (h0[k][f] + 1) & (kHashSlots - 1);
-                        const bool mine = o == empty || (o != (Slot)(unsigned)c &&
-                                                         claim_from(lds.set, c, h1));
-                        won[k] |= (unsigned)mine << f;
+                        if (o == empty)
+                            sl = (int)h0[k][f];
+                        else if (o != (Slot)(unsigned)c)
+                            sl = claim_from(lds.set, c, h1);
                     }
+                    slot[k][f] = sl;
+                    won[k] |= (unsigned)(sl >= 0) << f;
                 }
             }
         }
@@ -388,9 +392,19 @@ __device__ __forceinline__ int bfs_sweep(int4 *__restrict__ graph, int32_t *__re
     int sweep_total;
     int pos = produced + block_exclusive_scan(total, lds.scan, &sweep_total);
     // every use of the set in this sweep is done: empty it for the next sweep
-    // (the caller's barrier separates this from the next sweep's inserts)
-    for (int t = tid; t < kHashSlots; t += kCmThreads)
-        lds.set[t] = kLabel ? kPairEmpty : kHashEmpty;
+    // (the caller's barrier separates this from the next sweep's inserts).
+    // Every filled slot holds a cell that some thread proposed (with labels)
+    // or claimed, so these threads empty exactly the filled slots.
+    if (wave_busy) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                if (slot[k][f] >= 0)
+                    lds.set[slot[k][f]] = kLabel ? kPairEmpty : kHashEmpty;
+            }
+        }
+    }
     if (wave_busy) {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
