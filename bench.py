@@ -455,18 +455,23 @@ def main() -> int:
 
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
+    half = args.fv_steps // 2
+
     def job(record=None):
-        e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+        e0, e1, eh, e2, e3 = ev(), ev(), ev(), ev(), ev()
         e0.record(stream)
         fv.fv_renumber(s.ctx, fv.FV_ORDER_CM)
         fv.fv_upload_state_device(s.ctx, dU0)
         e1.record(stream)
-        fv.fv_step(s.ctx, args.fv_steps, dt)
+        # the same steps in two calls, with an event between the halves
+        fv.fv_step(s.ctx, half, dt)
+        eh.record(stream)
+        fv.fv_step(s.ctx, args.fv_steps - half, dt)
         e2.record(stream)
         fv.fv_download_state_device(s.ctx, dout)
         e3.record(stream)
         if record is not None:
-            record.append((e0, e1, e2, e3))
+            record.append((e0, e1, e2, e3, eh))
 
     log(f"warmup: {args.warmup} job(s)")
     for _ in range(args.warmup):
@@ -483,9 +488,11 @@ def main() -> int:
     wall = time.perf_counter() - t0
 
     layout_bytes = fv.fv_bytes_per_update(s.ctx)
-    renum_ms = [a.elapsed_time(b) for a, b, _, _ in marks]
-    step_ms = [b.elapsed_time(c) for _, b, c, _ in marks]
-    down_ms = [c.elapsed_time(d) for _, _, c, d in marks]
+    renum_ms = [a.elapsed_time(b) for a, b, _, _, _ in marks]
+    step_ms = [b.elapsed_time(c) for _, b, c, _, _ in marks]
+    first_half_ms = [b.elapsed_time(h) for _, b, _, _, h in marks]
+    second_half_ms = [h.elapsed_time(c) for _, _, c, _, h in marks]
+    down_ms = [c.elapsed_time(d) for _, _, c, d, _ in marks]
     ms_per_job = wall * 1e3 / args.steps
     value = n * args.fv_steps * args.steps / wall
     step_kernel_s = float(np.mean(step_ms)) * 1e-3 / args.fv_steps
@@ -586,6 +593,11 @@ def main() -> int:
         "breakdown": {
             "renumber_and_upload_ms": float(np.median(renum_ms)),
             "steps_ms": float(np.median(step_ms)),
+            # the job's steps split in halves: the first half includes the
+            # slow-down that follows the renumbering's near-idle chip
+            "first_half_step_us": (float(np.median(first_half_ms)) * 1e3 / half
+                                   if half else None),
+            "second_half_step_us": float(np.median(second_half_ms)) * 1e3 / (args.fv_steps - half),
             "download_ms": float(np.median(down_ms)),
             "step_only_cell_updates_per_s": n / step_kernel_s,
             "random_order_step_us": None if args.skip_random else random_step_s * 1e6,
