@@ -99,7 +99,7 @@ hipError_t launch_build_records(int32_t n, const int32_t *nb, int4 *rec, hipStre
 // on `side` and s waits for it before the labels are final.  Speculative: the
 // labels assume the search does not move, and the caller must launch the
 // confirming sweep itself once s holds nothing more that touches rec, rec2,
-// ordC, perm or state, wait for `probed`, and, if some probe[k] > state[k].y
+// ordC or state, wait for `probed`, and, if some probe[k] > state[k].y
 // (the eccentricity grew), renumber again without speculation.
 hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe, int32_t n,
                               int32_t n_seg, const int64_t *seg, int32_t *permA, int32_t *ordC,
@@ -109,14 +109,14 @@ hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe
 
 // The confirming sweep of each segment's first component on `side`, after
 // everything queued on s (event `labelled`), recorded as `probed`: the graph
-// renamed by the first labels into rec2 (ordC as its inverse), then the sweep
-// from the first pass's pick, whose eccentricity goes to probe[k].  Until
-// `probed`, side reads rec's neighbour fields, state and the first
-// components' labels in perm, and writes rec2, ordC and probe.
+// renamed by the first labels into rec2 (read from rec, whose marks are the
+// labels after the first pass), then the sweep from the first pass's pick,
+// whose eccentricity goes to probe[k].  Until `probed`, side reads rec and
+// state, and writes rec2, ordC (the sweep's frontier overflow) and probe.
 hipError_t launch_cm_confirm(const int4 *rec, int4 *rec2, const int4 *state, int32_t *probe,
                              int32_t n, int32_t n_seg, const int64_t *seg, int32_t *ordC,
-                             const int32_t *perm, hipStream_t s, hipStream_t side,
-                             hipEvent_t labelled, hipEvent_t probed);
+                             hipStream_t s, hipStream_t side, hipEvent_t labelled,
+                             hipEvent_t probed);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_iota(int32_t *p, int32_t count, hipStream_t s);

@@ -526,8 +526,8 @@ __device__ __forceinline__ BfsResult bfs_pass(int4 *__restrict__ graph, int32_t 
 //                        the result when the search does not move (the root
 //                        then stays the lowest id), eccentricity and pick;
 // and, on a second stream,
-//   cm_invert_kernel,    the component's graph renamed by those labels (rec2:
-//   cm_rename_kernel     neighbours as labels), in which every level is a
+//   cm_rename_kernel     the component's graph renamed by those labels (rec2:
+//                        neighbours as labels), in which every level is a
 //                        contiguous range and neighbours sit close;
 //   cm_probe_kernel      the sweep from the pick on rec2 (the search's
 //                        second step);
@@ -573,49 +573,39 @@ __device__ __forceinline__ int segment_of(int l, int n_seg, const int64_t *__res
     return lo;
 }
 
-// inv[perm[l]] = l for the labels l of each segment's first component;
-// root[s] = the label of the segment's pick (the probe sweep's root).
-__global__ void cm_invert_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict__ seg,
-                                 const int4 *__restrict__ state, const int32_t *__restrict__ perm,
-                                 int32_t *__restrict__ inv, int32_t *__restrict__ root)
-{
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= n)
-        return;
-    const int sg = segment_of(l, n_seg, seg);
-    if (l - (int)seg[sg] >= state[sg].x)
-        return;
-    const int c = perm[l];
-    inv[c] = l;
-    if (c == state[sg].z)
-        root[sg] = l;
-}
-
-// rec2[l] = the record of the cell labelled l with neighbours as labels (same
-// encoding as rec), for the labels of each segment's first component.  Reads only the neighbour
-// fields of rec (the finish kernel may be writing the marks of other
-// components' records beside it).
+// rec2[L] = the record of the cell v labelled L with neighbours as labels
+// (same encoding as rec), for the cells of each segment's first component,
+// read from the labelled records themselves (after the first pass a cell's
+// mark is its label); probe[s] = the label of the segment's pick (the probe
+// sweep's root).  Labels outside the first component's range (later
+// components, or cells not labelled yet) are skipped.
 __global__ void cm_rename_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict__ seg,
                                  const int4 *__restrict__ state, const int4 *__restrict__ rec,
-                                 const int32_t *__restrict__ perm, const int32_t *__restrict__ inv,
-                                 int4 *__restrict__ rec2)
+                                 int4 *__restrict__ rec2, int32_t *__restrict__ root)
 {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= n)
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n)
         return;
-    const int sg = segment_of(l, n_seg, seg);
-    if (l - (int)seg[sg] >= state[sg].x)
+    const int sg = segment_of(v, n_seg, seg);
+    const int s0 = (int)seg[sg];
+    const int4 st = state[sg];
+    const int4 r = rec[v];
+    const int L = r.w;
+    if (L < s0 || L - s0 >= st.x)
         return;
-    const int *r = reinterpret_cast<const int *>(rec + perm[l]);
+    const int *label = reinterpret_cast<const int *>(rec) + 3;  // label of cell x: label[4 x]
+    const int nbr[3] = {r.x, r.y, r.z};
     int q[3];
 #pragma unroll
     for (int f = 0; f < 3; ++f)
-        q[f] = r[f] >= 0 ? inv[r[f]] : ~inv[~r[f]];
-    rec2[l] = make_int4(q[0], q[1], q[2], ~((q[0] >= 0) + (q[1] >= 0) + (q[2] >= 0)));
+        q[f] = nbr[f] >= 0 ? label[4 * nbr[f]] : ~label[4 * ~nbr[f]];
+    rec2[L] = make_int4(q[0], q[1], q[2], ~((q[0] >= 0) + (q[1] >= 0) + (q[2] >= 0)));
+    if (v == st.z)
+        root[sg] = L;
 }
 
 // The sweep from the first component's pick on rec2, one workgroup per
-// segment: on entry probe[s] holds the pick's label (cm_invert_kernel), on
+// segment: on entry probe[s] holds the pick's label (cm_rename_kernel), on
 // exit the sweep's eccentricity.  It may run beside the finish kernel, so it
 // writes only rec2's marks, its own order ordC and probe, and reads nothing
 // the finish kernel writes (the pick it finds is not used).
@@ -783,23 +773,17 @@ hipError_t launch_build_records(int32_t n, const int32_t *nb, int4 *rec, hipStre
 
 hipError_t launch_cm_confirm(const int4 *rec, int4 *rec2, const int4 *state, int32_t *probe,
                              int32_t n, int32_t n_seg, const int64_t *seg, int32_t *ordC,
-                             const int32_t *perm, hipStream_t s, hipStream_t side,
-                             hipEvent_t labelled, hipEvent_t probed)
+                             hipStream_t s, hipStream_t side, hipEvent_t labelled,
+                             hipEvent_t probed)
 {
-    // on the second stream, after everything queued on s so far; ordC serves
-    // as the inverse of the first labels until the probe writes its own
-    // order there
+    // on the second stream, after everything queued on s so far
     hipError_t e = hipEventRecord(labelled, s);
     if (e != hipSuccess)
         return e;
     if ((e = hipStreamWaitEvent(side, labelled, 0)) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(cm_invert_kernel, dim3((n + 255) / 256), dim3(256), 0, side, n, n_seg, seg,
-                       state, perm, ordC, probe);
-    if ((e = hipGetLastError()) != hipSuccess)
-        return e;
     hipLaunchKernelGGL(cm_rename_kernel, dim3((n + 255) / 256), dim3(256), 0, side, n, n_seg, seg,
-                       state, rec, perm, ordC, rec2);
+                       state, rec, rec2, probe);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     hipLaunchKernelGGL(cm_probe_kernel, dim3(n_seg), dim3(kCmThreads), 0, side, rec2, seg, ordC,
@@ -821,7 +805,7 @@ hipError_t launch_cm_segments(int4 *rec, int4 *rec2, int4 *state, int32_t *probe
     if (e != hipSuccess)
         return e;
     if (!speculative) {
-        if ((e = launch_cm_confirm(rec, rec2, state, probe, n, n_seg, seg, ordC, perm, s, side,
+        if ((e = launch_cm_confirm(rec, rec2, state, probe, n, n_seg, seg, ordC, s, side,
                                    labelled, probed)) != hipSuccess)
             return e;
         if ((e = hipStreamWaitEvent(s, probed, 0)) != hipSuccess)

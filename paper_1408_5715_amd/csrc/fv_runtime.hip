@@ -335,8 +335,8 @@ fv_status cm_confirm(fv_ctx *c)
 {
     const CmScratch m(c);
     HIP_TRY(fvk::launch_cm_confirm(m.rec, m.rec2, c->cm_state, c->cm_probe, c->n, c->n_seg,
-                                   c->seg_dev, m.ordC, c->perm, c->stream, c->side,
-                                   c->ev_labelled, c->ev_probed));
+                                   c->seg_dev, m.ordC, c->stream, c->side, c->ev_labelled,
+                                   c->ev_probed));
     return FV_OK;
 }
 

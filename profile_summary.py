@@ -208,7 +208,7 @@ def main_renumber() -> int:
                 "void fv_step_kernel<256, true, true, true, false>")
     # (kernel, CUs it runs on, levels it walks): the labelling pass and the
     # confirming sweep run on one CU each
-    rows = [("cm_first_kernel", 1, 1366), ("cm_invert_kernel", 256, 0),
+    rows = [("cm_first_kernel", 1, 1366),
             ("cm_rename_kernel", 256, 0), ("cm_probe_kernel", 1, 1366),
             ("cm_finish_kernel", 1, 0), (step, 256, 0)]
     lines = ["| kernel | cycles | waves | VALU / wave | VMEM reads / wave | VALU busy / SIMD "
