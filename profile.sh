@@ -18,6 +18,11 @@
 # the 2,097,152-cell workload, for the renumbering kernels and the step.
 # Output rprof_*.  Summarise with python profile_summary.py renumber.
 #
+# `profile.sh hbm`: the step alone on the 2048 x 2048-quad mesh (8,388,608
+# cells, working set beyond the Infinity Cache; bench.py --workload hbm): a
+# kernel trace, then FETCH_SIZE and WRITE_SIZE with the calibration copy.
+# Output hprof_*.  Summarise with python profile_summary.py hbm.
+#
 # `profile.sh orders`: the random / AM1 / Cuthill-McKee comparison on the
 # 512 x 512-quad irregular mesh (tests/test_gpu_irregular.py) under the L2
 # hit and miss counters.  Output oprof_*.  Summarise with
@@ -40,6 +45,20 @@ if [ "${1:-}" = "renumber" ]; then
     timeout -s KILL 120 rocprofv3 --pmc TA_TA_BUSY TA_ADDR_STALLED_BY_TC_CYCLES TCP_TCC_READ_REQ \
         TCP_TCC_READ_REQ_LATENCY GRBM_GUI_ACTIVE SQ_INSTS_LDS -f csv \
         -d "$OUT/rprof_mem" -o mem -- "${JOB[@]}" > "$OUT/rprof_mem.log" 2>&1
+    echo "[profile] done" >&2
+    exit 0
+fi
+if [ "${1:-}" = "hbm" ]; then
+    HBM=(python3 "$ROOT/bench.py" --workload hbm --hbm-N 2048)
+    echo "[profile] hbm: kernel trace" >&2
+    timeout -k 10 300 rocprofv3 --kernel-trace --stats -f csv -d "$OUT/hprof_trace" -o trace -- \
+        "${HBM[@]}" --fv-steps 200 > "$OUT/hprof_trace.log" 2>&1
+    echo "[profile] hbm: FETCH_SIZE" >&2
+    timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE -f csv -d "$OUT/hprof_fetch" -o fetch -- \
+        "${HBM[@]}" --fv-steps 20 --probe-copy > "$OUT/hprof_fetch.log" 2>&1
+    echo "[profile] hbm: WRITE_SIZE" >&2
+    timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE -f csv -d "$OUT/hprof_write" -o write -- \
+        "${HBM[@]}" --fv-steps 20 --probe-copy > "$OUT/hprof_write.log" 2>&1
     echo "[profile] done" >&2
     exit 0
 fi

@@ -41,23 +41,33 @@ def counters(path, counter):
     return out
 
 
-def main() -> int:
+def trace_table(prefix: str) -> list[str]:
+    """Per-kernel statistics of the kernel trace run."""
     lines = []
-    stats = list(csv.DictReader(open(os.path.join(OUT, "prof_trace", "trace_kernel_stats.csv"))))
+    stats = list(csv.DictReader(open(os.path.join(OUT, f"{prefix}_trace",
+                                                  "trace_kernel_stats.csv"))))
     lines.append("| kernel | calls | avg us | min us | max us | share |")
     lines.append("|---|---|---|---|---|---|")
     for r in stats:
         lines.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                      f"{float(r['Percentage']):.1f}% |")
-    f = counters(os.path.join(OUT, "prof_fetch", "fetch_counter_collection.csv"), "FETCH_SIZE")
-    w = counters(os.path.join(OUT, "prof_write", "write_counter_collection.csv"), "WRITE_SIZE")
+    return lines
+
+
+def byte_table(prefix: str, cells: int):
+    """FETCH_SIZE / WRITE_SIZE per launch, scaled by the copy kernel's
+    readings; returns the lines and the step kernel's (fetch, write) bytes."""
+    lines = []
+    f = counters(os.path.join(OUT, f"{prefix}_fetch", "fetch_counter_collection.csv"),
+                 "FETCH_SIZE")
+    w = counters(os.path.join(OUT, f"{prefix}_write", "write_counter_collection.csv"),
+                 "WRITE_SIZE")
     copy = "torch elementwise copy (mul by 1)"
     # the first elementwise launch is the fill of the source (no read)
     fcopy = st.mean(f[copy][1:]) * 1024
     wcopy = st.mean(w[copy]) * 1024
     fs, ws = COPY_BYTES / fcopy, COPY_BYTES / wcopy
-    lines.append("")
     lines.append(f"Copy calibration: FETCH_SIZE reads {fcopy / 2**20:.1f} MiB and WRITE_SIZE "
                  f"{wcopy / 2**20:.1f} MiB for 256 MiB each; scale factors {fs:.3f} and {ws:.3f}.")
     lines.append("")
@@ -71,13 +81,22 @@ def main() -> int:
         fb = st.mean(f[k]) * 1024 * fs
         wb = st.mean(w[k]) * 1024 * ws
         lines.append(f"| {k} | {len(f[k])} | {fb / 2**20:.1f} | {wb / 2**20:.1f} | "
-                     f"{(fb + wb) / CELLS:.1f} |")
+                     f"{(fb + wb) / cells:.1f} |")
         if "fv_step_kernel" in k:
             step = (round(fb), round(wb))
     if step:
         lines.append("")
         lines.append(f"fv_step_kernel per launch (scaled): fetch {step[0]:,} B + write {step[1]:,} B "
                      f"= {step[0] + step[1]:,} B")
+    return lines, step, (fs, ws)
+
+
+def main() -> int:
+    lines = trace_table("prof")
+    lines.append("")
+    table, step, (fs, ws) = byte_table("prof", CELLS)
+    lines += table
+    if step:
         # machine-readable line bench.py reads as its `traffic`, valid for the
         # step kernel source it was measured with
         with open(os.path.join(ROOT, "paper_1408_5715_amd", "csrc", "fv_step.hip"), "rb") as fh:
@@ -105,6 +124,39 @@ def main() -> int:
             if line.startswith("{"):
                 lines.append("")
                 lines.append("bench.py line of the traced run: `" + line.strip() + "`")
+    print("\n".join(lines))
+    return 0
+
+
+def main_hbm() -> int:
+    """profile.sh hbm: the step on the 2048 x 2048-quad mesh."""
+    cells = 2 * 2048 * 2048
+    lines = trace_table("hprof")
+    # the step's launches in order: the warm-up ones, then the timed ones
+    path = os.path.join(OUT, "hprof_trace", "trace_kernel_trace.csv")
+    rows = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                  for r in csv.DictReader(open(path)) if "fv_step_kernel" in r["Kernel_Name"])
+    us = [(e - b) / 1e3 for b, e in rows]
+    if len(us) >= 40:
+        lines.append("")
+        lines.append("fv_step_kernel launches in order, mean us per block of 20: "
+                     + ", ".join(f"{st.mean(us[i:i + 20]):.1f}" for i in range(0, len(us), 20)))
+        half = len(us) // 2
+        lines.append("")
+        lines.append(f"fv_step_kernel: first {half} launches {st.mean(us[:half]):.2f} us, "
+                     f"last {len(us) - half} launches {st.mean(us[half:]):.2f} us "
+                     f"({cells * 96 / st.mean(us[half:]) / 1e3:.0f} GB/s at 96 B per cell)")
+    lines.append("")
+    table, step, _ = byte_table("hprof", cells)
+    lines += table
+    for name in ("hprof_trace.log", "hprof_fetch.log"):
+        log = os.path.join(OUT, name)
+        if os.path.exists(log):
+            for line in open(log):
+                if line.startswith("{"):
+                    lines.append("")
+                    lines.append(f"bench.py line of the {name.split('_')[1].split('.')[0]} run: `"
+                                 + line.strip() + "`")
     print("\n".join(lines))
     return 0
 
@@ -243,6 +295,8 @@ def main_renumber() -> int:
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "learned":
         sys.exit(main_learned())
+    if len(sys.argv) > 1 and sys.argv[1] == "hbm":
+        sys.exit(main_hbm())
     if len(sys.argv) > 1 and sys.argv[1] == "orders":
         sys.exit(main_orders())
     if len(sys.argv) > 1 and sys.argv[1] == "renumber":
