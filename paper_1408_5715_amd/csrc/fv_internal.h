@@ -7,7 +7,10 @@
 //   nb      int32  [3][ld]    neighbour across face f (structure of arrays)
 //   nrm     double [6][ld]    nx_0, ny_0, nx_1, ny_1, nx_2, ny_2
 //   inv_area double [ld]      1 / V_T
-//   nb16    short4 [ld]       neighbour offsets j - i, when they fit in 16 bits
+//   nb16    short4 [ld]       neighbour offsets j - i, when they fit in 16 bits;
+//                             interleaved with dt / V as (short4, double) [ld]
+//                             on a mesh beyond the Infinity Cache
+//                             (narrow_interleaved)
 //   nfx     int4   [ld]       first two normals in fixed point, when exact
 #pragma once
 
@@ -17,10 +20,26 @@
 
 namespace fvk {
 
+// Bytes of the compact layout's working set per cell (two states, offsets,
+// fixed-point normals, dt/V) and the Infinity Cache of MI355X.  A compact
+// mesh whose working set exceeds the cache is stepped with non-temporal
+// reads of its per-cell arrays and keeps its 16-bit offsets interleaved with
+// dt/V (16 bytes per cell: one load brings both, before the neighbour
+// gathers).  Within the cache the offsets are a plain short4 array and dt/V
+// is read from coef after the flux (the critical first load then touches
+// half as many cache lines).
+constexpr int64_t kCompactBytes = 2 * 32 + 8 + 16 + 8;
+constexpr int64_t kInfinityCache = int64_t(256) << 20;
+inline bool narrow_interleaved(int64_t n, bool fixed)
+{
+    return fixed && n * kCompactBytes > kInfinityCache;
+}
 
 // One forward-Euler Lax-Friedrichs step over all cells: Un = U - coef sum F
 // with coef[i] = dt / V_i.
-// narrow: read neighbours from nb16 (16-bit offsets) instead of nb.
+// narrow: read neighbours from nb16 (16-bit offsets) instead of nb; with
+// narrow_interleaved(n, fixed && closed), nb16 is the interleaved array and
+// dt/V comes from it instead of coef.
 // closed: take the third normal as -(n_0 + n_1) instead of reading it.
 // fixed (with closed): read the first two normals from nfx (fixed point).
 // block: 128, 256 or 512 threads; grid: 0 = one workgroup per tile of
@@ -35,14 +54,18 @@ hipError_t launch_step(int32_t n, int32_t ld, const double4 *U, double4 *Un, con
 hipError_t launch_fixed_normals(int32_t n, int32_t ld, const double *nrm, int4 *nfx,
                                 hipStream_t s);
 
-// coef[i] = dt[s] * inv_area[i], s the segment of cell i.
+// coef[i] = dt[s] * inv_area[i], s the segment of cell i; with an
+// interleaved nb16 array (else null), its dt/V slots receive the same values.
 hipError_t launch_coef(int32_t n, int32_t n_seg, const int64_t *seg, const double *dt,
-                       const double *inv_area, double *coef, hipStream_t s);
+                       const double *inv_area, double *coef, short4 *nb16_interleaved,
+                       hipStream_t s);
 
-// nb16[i] = (nb[0][i] - i, nb[1][i] - i, nb[2][i] - i, 0) as 16-bit offsets;
-// *too_far = 1 when some offset does not fit (it must be 0 before).
+// nb16[stride * i] = (nb[0][i] - i, nb[1][i] - i, nb[2][i] - i, 0) as 16-bit
+// offsets (stride 1: plain array, 2: interleaved with dt/V, whose slots are
+// left alone); *too_far = 1 when some offset does not fit (it must be 0
+// before).
 hipError_t launch_narrow_offsets(int32_t n, int32_t ld, const int32_t *nb, short4 *nb16,
-                                 int32_t *too_far, hipStream_t s);
+                                 int stride, int32_t *too_far, hipStream_t s);
 
 // Cotangent of one step's input from the cotangent of its output, on arrays
 // in any one numbering (mesh arrays nb [3][ld], nrm [6][ld], inv_area [ld]
@@ -62,9 +85,11 @@ constexpr int kCorrParams = 12 * 64 + 64 + 64 * 64 + 64 + 64 * 4 + 4;  // 5252
 constexpr int kCorrFragShorts = 24 * 64 * 4;
 constexpr int kCorrBias = 144;
 void pack_correction(const float *params, short *frags, float *bias);
+// nb16_stride: 1 for the plain offset array, 2 for the interleaved one.
 hipError_t launch_step_learned(int32_t n, int32_t ld, const double4 *U, double4 *Un,
-                               const int32_t *nb, const short4 *nb16, const double *nrm,
-                               const double *coef, const double *inv_area, const short *frags,
+                               const int32_t *nb, const short4 *nb16, int nb16_stride,
+                               const double *nrm, const double *coef, const double *inv_area,
+                               const short *frags,
                                const float *bias, double gamma, bool narrow, bool closed, int grid,
                                hipStream_t s);
 

@@ -201,10 +201,10 @@ __device__ __forceinline__ void rotate(const f4 &y, double ex, double ey, double
 
 template <bool kNarrow>
 __device__ __forceinline__ int neighbour(int i, int f, int32_t ld, const int32_t *nb,
-                                         const short4 *nb16)
+                                         const short4 *nb16, int nb16_stride)
 {
     if constexpr (kNarrow) {
-        const short4 o = nb16[i];
+        const short4 o = nb16[(int64_t)nb16_stride * i];
         return i + (f == 0 ? o.x : (f == 1 ? o.y : o.z));
     } else {
         return nb[f * ld + i];
@@ -302,7 +302,7 @@ __device__ __forceinline__ void stage_weights(short *Wl, float *Bl, const short 
 template <bool kNarrow, bool kClosed>
 __global__ __launch_bounds__(kBlock, 3) void fv_step_learned_kernel(
     int32_t n, int32_t ld, const double4 *__restrict__ U, double4 *__restrict__ Un,
-    const int32_t *__restrict__ nb, const short4 *__restrict__ nb16,
+    const int32_t *__restrict__ nb, const short4 *__restrict__ nb16, int nb16_stride,
     const double *__restrict__ nrm, const double *__restrict__ coef,
     const double *__restrict__ inv_area, const short *__restrict__ frags,
     const float *__restrict__ bias, double gamma)
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kBlock, 3) void fv_step_learned_kernel(
         for (int f = 0; f < 3; ++f) {
             double len = 1.0, ex = 1.0, ey = 0.0;
             if (live) {
-                const int j = neighbour<kNarrow>(i, f, ld, nb, nb16);
+                const int j = neighbour<kNarrow>(i, f, ld, nb, nb16, nb16_stride);
                 double nx, ny;
                 normal<kClosed>(i, f, ld, nrm, nx, ny);
                 const double4 Uj = U[j];
@@ -871,8 +871,9 @@ hipError_t launch_adjoint_learned(int32_t n, int32_t ld, const double4 *U, const
 }
 
 hipError_t launch_step_learned(int32_t n, int32_t ld, const double4 *U, double4 *Un,
-                               const int32_t *nb, const short4 *nb16, const double *nrm,
-                               const double *coef, const double *inv_area, const short *frags,
+                               const int32_t *nb, const short4 *nb16, int nb16_stride,
+                               const double *nrm, const double *coef, const double *inv_area,
+                               const short *frags,
                                const float *bias, double gamma, bool narrow, bool closed, int grid,
                                hipStream_t s)
 {
@@ -882,16 +883,16 @@ hipError_t launch_step_learned(int32_t n, int32_t ld, const double4 *U, double4 
     const int G = (grid <= 0 || grid > tiles) ? (tiles < 8192 ? tiles : 8192) : grid;
     if (narrow && closed)
         hipLaunchKernelGGL((fv_step_learned_kernel<true, true>), dim3(G), dim3(kBlock), 0, s, n, ld,
-                           U, Un, nb, nb16, nrm, coef, inv_area, frags, bias, gamma);
+                           U, Un, nb, nb16, nb16_stride, nrm, coef, inv_area, frags, bias, gamma);
     else if (narrow)
         hipLaunchKernelGGL((fv_step_learned_kernel<true, false>), dim3(G), dim3(kBlock), 0, s, n,
-                           ld, U, Un, nb, nb16, nrm, coef, inv_area, frags, bias, gamma);
+                           ld, U, Un, nb, nb16, nb16_stride, nrm, coef, inv_area, frags, bias, gamma);
     else if (closed)
         hipLaunchKernelGGL((fv_step_learned_kernel<false, true>), dim3(G), dim3(kBlock), 0, s, n,
-                           ld, U, Un, nb, nb16, nrm, coef, inv_area, frags, bias, gamma);
+                           ld, U, Un, nb, nb16, nb16_stride, nrm, coef, inv_area, frags, bias, gamma);
     else
         hipLaunchKernelGGL((fv_step_learned_kernel<false, false>), dim3(G), dim3(kBlock), 0, s, n,
-                           ld, U, Un, nb, nb16, nrm, coef, inv_area, frags, bias, gamma);
+                           ld, U, Un, nb, nb16, nb16_stride, nrm, coef, inv_area, frags, bias, gamma);
     return hipGetLastError();
 }
 

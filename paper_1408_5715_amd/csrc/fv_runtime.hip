@@ -66,7 +66,9 @@ struct Layout {
         const size_t ld = (size_t)leading_dim(n);
         U = align_up(ld * 32);
         nb = align_up(ld * 3 * 4);
-        nb16 = align_up(ld * 8);
+        // 16-bit offsets, interleaved with dt/V on a mesh beyond the
+        // Infinity Cache
+        nb16 = align_up(ld * 16);
         nfx = align_up(ld * 16);
         nrm = align_up(ld * 6 * 8);
         area = align_up(ld * 8);
@@ -106,7 +108,8 @@ struct fv_ctx {
     double *nrm_o = nullptr;
     double *area_o = nullptr;
     int32_t *nb_w = nullptr;  // working (renumbered) order
-    short4 *nb16_w = nullptr; // ... as 16-bit offsets, valid when `narrow`
+    short4 *nb16_w = nullptr; // ... as 16-bit offsets, valid when `narrow` (interleaved with
+                              // dt / V when `interleaved`)
     int4 *nfx_w = nullptr;    // first two normals of the working order in fixed point, when `fixed`
     double *nrm_w = nullptr;
     double *inv_area_w = nullptr;
@@ -149,6 +152,7 @@ struct fv_ctx {
     bool closed = false;  // every cell: n_2 == -(n_0 + n_1) exactly
     bool fixed = false;   // every n_0, n_1 component is k 2^-32, |k| < 2^31 (and `closed`)
     bool narrow = false;  // every neighbour offset of the working order fits in 16 bits
+    bool interleaved = false;  // nb16 interleaves the offsets with dt / V (fvk::narrow_interleaved)
     bool cm_passes = false;  // passes_dev holds the counts of a renumbering of this mesh
 };
 
@@ -265,7 +269,8 @@ fv_status regather_geometry(fv_ctx *c)
                                         c->area_o, c->nb_w, c->nrm_w, c->inv_area_w, c->stream));
     int32_t *dflag = reinterpret_cast<int32_t *>(c->small + 192);
     HIP_TRY(fvk::launch_fill_i32(dflag, 0, 1, c->stream));
-    HIP_TRY(fvk::launch_narrow_offsets(c->n, c->ld, c->nb_w, c->nb16_w, dflag, c->stream));
+    HIP_TRY(fvk::launch_narrow_offsets(c->n, c->ld, c->nb_w, c->nb16_w, c->interleaved ? 2 : 1,
+                                       dflag, c->stream));
     if (c->fixed) {
         HIP_TRY(fvk::launch_fixed_normals(c->n, c->ld, c->nrm_w, c->nfx_w, c->stream));
     }
@@ -351,7 +356,7 @@ fv_status ensure_coef(fv_ctx *c, const double *dt)
     HIP_TRY(hipMemcpyAsync(c->dt_dev, dt, (size_t)c->n_seg * sizeof(double),
                            hipMemcpyHostToDevice, c->stream));
     HIP_TRY(fvk::launch_coef(c->n, c->n_seg, c->seg_dev, c->dt_dev, c->inv_area_w, c->coef,
-                             c->stream));
+                             c->interleaved ? c->nb16_w : nullptr, c->stream));
     // the host array of dt values is read by the copy; keep it alive until then
     if (fv_status st = wait_stream(c))
         return st;
@@ -377,8 +382,9 @@ hipError_t launch_one(fv_ctx *c, int from, hipStream_t st)
 {
     if (c->corr_on)
         return fvk::launch_step_learned(c->n, c->ld, c->U[from], c->U[from ^ 1], c->nb_w,
-                                        c->nb16_w, c->nrm_w, c->coef, c->inv_area_w, c->corr_frags,
-                                        c->corr_bias, c->gamma, c->narrow, c->closed, c->grid, st);
+                                        c->nb16_w, c->interleaved ? 2 : 1, c->nrm_w, c->coef,
+                                        c->inv_area_w, c->corr_frags, c->corr_bias, c->gamma,
+                                        c->narrow, c->closed, c->grid, st);
     return fvk::launch_step(c->n, c->ld, c->U[from], c->U[from ^ 1], c->nb_w, c->nb16_w,
                             c->nrm_w, c->nfx_w, c->coef, c->gamma, c->narrow, c->closed, c->fixed,
                             c->block, c->grid, st);
@@ -640,6 +646,7 @@ fv_status upload(fv_ctx *c, int32_t n_seg, const int64_t *seg, const int32_t *nb
     drop_graph(c);
     c->closed = normals_closed(c->n, nrm);
     c->fixed = c->closed && normals_fixed(c->n, nrm);
+    c->interleaved = fvk::narrow_interleaved(c->n, c->fixed);
     c->n_seg = n_seg;
     c->seg_host.assign(seg, seg + n_seg + 1);
     HIP_TRY(hipMemcpyAsync(c->seg_dev, c->seg_host.data(), (n_seg + 1) * sizeof(int64_t),

@@ -26,6 +26,8 @@
 //   - kNarrow: neighbour j of cell i stored as the 16-bit offset j - i
 //     (four shorts, 8 bytes) instead of three 32-bit indices; used when every
 //     offset fits, which the Cuthill-McKee order makes true on large meshes.
+//     Beyond the Infinity Cache (kStream) the offsets are interleaved with
+//     the cell's dt / V_T, so one 16-byte load brings both.
 //   - kClosed: the third normal read as -(n_0 + n_1) instead of from memory;
 //     used when every cell's stored normals satisfy n_2 == -(n_0 + n_1)
 //     exactly, so the value is bit-identical to the stored one.
@@ -132,12 +134,19 @@ __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__
                                             const int4 *__restrict__ nfx,
                                             const double *__restrict__ coef, double gamma)
 {
+    static_assert(kNarrow || !kStream, "the streaming step reads the interleaved offsets");
     int js[3];
+    // coef = dt / V_T, formed as dt * (1 / V_T) by coef_kernel: with kStream
+    // beside the offsets, else from coef after the flux
+    double k;
     if constexpr (kNarrow) {
         short4 o;
         {
             // the four 16-bit offsets as one 8-byte word
-            const long long q = read_once<kStream>(reinterpret_cast<const long long *>(nb16) + i);
+            const long long *w = reinterpret_cast<const long long *>(nb16);
+            const long long q = read_once<kStream>(kStream ? w + 2 * (int64_t)i : w + i);
+            if constexpr (kStream)
+                k = __longlong_as_double(read_once<kStream>(w + 2 * (int64_t)i + 1));
             o = *reinterpret_cast<const short4 *>(&q);
         }
         js[0] = i + o.x;
@@ -203,8 +212,8 @@ __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__
         a3 += 0.5 * ((Ui.w + L.p) * VL + (Uj.w + R.p) * VR) - 0.5 * s * (Uj.w - Ui.w);
     }
 
-    // coef = dt / V_T, formed as dt * (1 / V_T) by coef_kernel
-    const double k = read_once<kStream>(coef + i);
+    if constexpr (!kStream)
+        k = coef[i];
     double4 out;
     out.x = Ui.x - k * a0;
     out.y = Ui.y - k * a1;
@@ -247,10 +256,11 @@ __global__ __launch_bounds__(kBlock) void fv_step_kernel(
 }
 
 // coef[i] = dt[s] * inv_area[i] for the segment s holding i (seg: n_seg + 1
-// increasing offsets).
+// increasing offsets); also into the dt/V slots of an interleaved offset
+// array when there is one.
 __global__ void coef_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict__ seg,
                             const double *__restrict__ dt, const double *__restrict__ inv_area,
-                            double *__restrict__ coef)
+                            double *__restrict__ coef, short4 *__restrict__ nb16_interleaved)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n)
@@ -263,7 +273,10 @@ __global__ void coef_kernel(int32_t n, int32_t n_seg, const int64_t *__restrict_
         else
             hi = mid - 1;
     }
-    coef[i] = dt[lo] * inv_area[i];
+    const double k = dt[lo] * inv_area[i];
+    coef[i] = k;
+    if (nb16_interleaved)
+        reinterpret_cast<double *>(nb16_interleaved)[2 * (int64_t)i + 1] = k;
 }
 
 template <int kBlock, bool kNarrow, bool kClosed, bool kFixed, bool kStream = false>
@@ -275,12 +288,6 @@ void launch_variant(int G, int32_t n, int32_t ld, const double4 *U, double4 *Un,
                        dim3(kBlock), 0, s, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma);
 }
 
-// Bytes of the compact layout's working set per cell (two states, offsets,
-// fixed-point normals, dt/V) and the Infinity Cache of MI355X: a larger
-// working set streams the per-cell arrays past it.
-constexpr int64_t kCompactBytes = 2 * 32 + 8 + 16 + 8;
-constexpr int64_t kInfinityCache = int64_t(256) << 20;
-
 template <int kBlock>
 hipError_t launch_step_block(int32_t n, int32_t ld, const double4 *U, double4 *Un,
                              const int32_t *nb, const short4 *nb16, const double *nrm,
@@ -290,7 +297,7 @@ hipError_t launch_step_block(int32_t n, int32_t ld, const double4 *U, double4 *U
     const int tiles = (n + kBlock - 1) / kBlock;
     const int G = (grid <= 0 || grid > tiles) ? tiles : grid;
     fixed = fixed && closed;
-    if (narrow && fixed && (int64_t)n * kCompactBytes > kInfinityCache)
+    if (narrow && narrow_interleaved(n, fixed))
         launch_variant<kBlock, true, true, true, true>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef,
                                                         gamma, s);
     else if (narrow && fixed)
@@ -308,10 +315,12 @@ hipError_t launch_step_block(int32_t n, int32_t ld, const double4 *U, double4 *U
     return hipGetLastError();
 }
 
-// 16-bit neighbour offsets of the working order; *too_far = 1 (every writer
-// stores the same value) if some offset does not fit.
+// 16-bit neighbour offsets of the working order at nb16[stride * i];
+// *too_far = 1 (every writer stores the same value) if some offset does not
+// fit.
 __global__ void narrow_offsets_kernel(int32_t n, int32_t ld, const int32_t *__restrict__ nb,
-                                      short4 *__restrict__ nb16, int32_t *__restrict__ too_far)
+                                      short4 *__restrict__ nb16, int stride,
+                                      int32_t *__restrict__ too_far)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n)
@@ -319,7 +328,7 @@ __global__ void narrow_offsets_kernel(int32_t n, int32_t ld, const int32_t *__re
     const int o0 = nb[i] - i, o1 = nb[ld + i] - i, o2 = nb[2 * ld + i] - i;
     const bool fits = o0 >= -32768 && o0 <= 32767 && o1 >= -32768 && o1 <= 32767 &&
                       o2 >= -32768 && o2 <= 32767;
-    nb16[i] = make_short4((short)o0, (short)o1, (short)o2, 0);
+    nb16[(int64_t)stride * i] = make_short4((short)o0, (short)o1, (short)o2, 0);
     if (!fits)
         *too_far = 1;
 }
@@ -374,22 +383,23 @@ hipError_t launch_fixed_normals(int32_t n, int32_t ld, const double *nrm, int4 *
 }
 
 hipError_t launch_coef(int32_t n, int32_t n_seg, const int64_t *seg, const double *dt,
-                       const double *inv_area, double *coef, hipStream_t s)
+                       const double *inv_area, double *coef, short4 *nb16_interleaved,
+                       hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(coef_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, n_seg, seg, dt,
-                       inv_area, coef);
+                       inv_area, coef, nb16_interleaved);
     return hipGetLastError();
 }
 
 hipError_t launch_narrow_offsets(int32_t n, int32_t ld, const int32_t *nb, short4 *nb16,
-                                 int32_t *too_far, hipStream_t s)
+                                 int stride, int32_t *too_far, hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(narrow_offsets_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, ld, nb,
-                       nb16, too_far);
+                       nb16, stride, too_far);
     return hipGetLastError();
 }
 
