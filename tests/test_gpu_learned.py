@@ -153,6 +153,25 @@ def test_layout_variants(torch, closed):
     assert err <= TWO_FLIPS
 
 
+def test_interleaved_offsets_bitwise(torch):
+    """A mesh beyond the Infinity Cache (1200 x 1200 quads, 2,880,000
+    cells) keeps its 16-bit offsets interleaved with dt/V once renumbered,
+    and the corrected step reads them at a 16-byte stride.  The corrected
+    step gives the same bits in any cell order, so the renumbered run and
+    the uploaded-order run (32-bit ids) must agree bit for bit."""
+    from gpu_helpers import bumps_case
+
+    log("corrected step, interleaved offsets, 1200")
+    m, U0, dt = bumps_case(1200)
+    assert m.n * 96 > 256 << 20
+    p = learned_ref.random_params(4)
+    a = run(m, U0, dt, 2, p, fv.FV_ORDER_CM)
+    b = run(m, U0, dt, 2, p, fv.FV_ORDER_IDENTITY)
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    plain = run(m, U0, dt, 2, None, fv.FV_ORDER_CM)
+    assert not np.array_equal(a, plain)
+
+
 def test_graph_replays_and_tiny_meshes(torch):
     """A captured graph of corrected steps replays to the eager bits (several
     replays, eager work in between), and the smallest meshes (2 x 2 quads,

@@ -420,9 +420,11 @@ def test_streaming_step_equals_cached_step_bitwise(torch):
     """A mesh whose compact working set (96 B per cell) exceeds the 256 MB
     Infinity Cache (1200 x 1200 quads, 2,880,000 cells: 276 MB) takes the
     step variant with non-temporal reads of its per-cell arrays once
-    renumbered; on the uploaded (random) order it takes the 32-bit index
-    variant without them.  A step gives the same bits in any cell order, so
-    the two runs must agree bit for bit."""
+    renumbered, with its 16-bit offsets interleaved with dt/V; on the
+    uploaded (random) order it takes the 32-bit index variant without them.
+    A step gives the same bits in any cell order, so the two runs must agree
+    bit for bit, also after a change of dt (which rewrites the interleaved
+    dt/V)."""
     log("streaming step 1200")
     m, U0, dt = bumps_case(1200)
     assert m.n * 96 > 256 << 20
@@ -433,9 +435,11 @@ def test_streaming_step_equals_cached_step_bitwise(torch):
         a.renumber(fv.FV_ORDER_CM)
         assert a.bytes_per_update() == 96
         a.step(5, dt)
+        a.step(3, 0.5 * dt)
         got = a.download()
         b.upload_state(U0)
         b.step(5, dt)
+        b.step(3, 0.5 * dt)
         ref = b.download()
     finally:
         a.close()
