@@ -190,7 +190,9 @@ def test_c3_full_batch(torch, tmp_path):
     """The 64-mesh batch at full size (about 12M cells), renumbered per mesh on
     the GPU, 500 steps in the autotuned launch shape: the smallest mesh
     matches the oracle, a mid-size mesh matches its own single-mesh run
-    bitwise, and every mesh conserves mass, momentum and energy."""
+    bitwise, and every mesh conserves mass, momentum and energy.  The batch
+    is beyond the Infinity Cache, so it runs the streaming step with its
+    offsets interleaved with per-mesh dt/V; the single-mesh runs do not."""
     from fvgen.batch import batch_workload, concat
     from paper_1408_5715_amd import autotune
 
