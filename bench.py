@@ -337,7 +337,7 @@ def bench_hbm(args, dev) -> int:
         probe_copy(dev)
     N = args.hbm_N if args.hbm_N > 0 else 2048
     fv_steps = args.fv_steps if args.fv_steps != 1000 else 200
-    c = hbm_resident_step(dev, N, fv_steps, warm_steps=args.hbm_warm)
+    c = hbm_resident_step(dev, N, fv_steps, snap_bits=args.snap_bits, warm_steps=args.hbm_warm)
     torch.cuda.synchronize()
     rec = {
         "metric": "cell-updates/s",
@@ -464,6 +464,9 @@ def main() -> int:
                     help="quads per side of the HBM-resident step timing (0: skip)")
     ap.add_argument("--hbm-warm", type=int, default=200,
                     help="untimed steps before the timed ones of --workload hbm")
+    ap.add_argument("--snap-bits", type=int, default=32,
+                    help="--workload hbm: coordinates on a 2^-bits grid (32: the compact "
+                         "96-byte layout; 40: float64 normals, 112 bytes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batch", action="store_true",
                     help="leave the 64-mesh batch case out of the default line")

@@ -20,25 +20,29 @@
 
 namespace fvk {
 
-// Bytes of the compact layout's working set per cell (two states, offsets,
-// fixed-point normals, dt/V) and the Infinity Cache of MI355X.  A compact
-// mesh whose working set exceeds the cache is stepped with non-temporal
-// reads of its per-cell arrays and keeps its 16-bit offsets interleaved with
-// dt/V (16 bytes per cell: one load brings both, before the neighbour
-// gathers).  Within the cache the offsets are a plain short4 array and dt/V
-// is read from coef after the flux (the critical first load then touches
-// half as many cache lines).
-constexpr int64_t kCompactBytes = 2 * 32 + 8 + 16 + 8;
+// Bytes of the working set per cell with 16-bit offsets (two states,
+// offsets, dt/V, and the normals: 16 B in fixed point, 32 B with the third
+// derived, 48 B all stored) and the Infinity Cache of MI355X.  A mesh whose
+// working set exceeds the cache is stepped with non-temporal reads of its
+// per-cell arrays and keeps its 16-bit offsets interleaved with dt/V (16
+// bytes per cell: one load brings both, before the neighbour gathers).
+// Within the cache the offsets are a plain short4 array and dt/V is read
+// from coef after the flux (the critical first load then touches half as
+// many cache lines).
 constexpr int64_t kInfinityCache = int64_t(256) << 20;
-inline bool narrow_interleaved(int64_t n, bool fixed)
+inline int64_t narrow_bytes(bool closed, bool fixed)
 {
-    return fixed && n * kCompactBytes > kInfinityCache;
+    return 2 * 32 + 8 + 8 + (fixed && closed ? 16 : (closed ? 32 : 48));
+}
+inline bool narrow_interleaved(int64_t n, bool closed, bool fixed)
+{
+    return n * narrow_bytes(closed, fixed) > kInfinityCache;
 }
 
 // One forward-Euler Lax-Friedrichs step over all cells: Un = U - coef sum F
 // with coef[i] = dt / V_i.
 // narrow: read neighbours from nb16 (16-bit offsets) instead of nb; with
-// narrow_interleaved(n, fixed && closed), nb16 is the interleaved array and
+// narrow_interleaved(n, closed, fixed), nb16 is the interleaved array and
 // dt/V comes from it instead of coef.
 // closed: take the third normal as -(n_0 + n_1) instead of reading it.
 // fixed (with closed): read the first two normals from nfx (fixed point).

@@ -646,7 +646,7 @@ fv_status upload(fv_ctx *c, int32_t n_seg, const int64_t *seg, const int32_t *nb
     drop_graph(c);
     c->closed = normals_closed(c->n, nrm);
     c->fixed = c->closed && normals_fixed(c->n, nrm);
-    c->interleaved = fvk::narrow_interleaved(c->n, c->fixed);
+    c->interleaved = fvk::narrow_interleaved(c->n, c->closed, c->fixed);
     c->n_seg = n_seg;
     c->seg_host.assign(seg, seg + n_seg + 1);
     HIP_TRY(hipMemcpyAsync(c->seg_dev, c->seg_host.data(), (n_seg + 1) * sizeof(int64_t),

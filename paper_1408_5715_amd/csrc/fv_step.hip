@@ -27,7 +27,8 @@
 //     (four shorts, 8 bytes) instead of three 32-bit indices; used when every
 //     offset fits, which the Cuthill-McKee order makes true on large meshes.
 //     Beyond the Infinity Cache (kStream) the offsets are interleaved with
-//     the cell's dt / V_T, so one 16-byte load brings both.
+//     the cell's dt / V_T, so one 16-byte load brings both, and the per-cell
+//     arrays are read with non-temporal loads.
 //   - kClosed: the third normal read as -(n_0 + n_1) instead of from memory;
 //     used when every cell's stored normals satisfy n_2 == -(n_0 + n_1)
 //     exactly, so the value is bit-identical to the stored one.
@@ -135,16 +136,16 @@ __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__
                                             const double *__restrict__ coef, double gamma)
 {
     static_assert(kNarrow || !kStream, "the streaming step reads the interleaved offsets");
-    // In the compact layout (kNarrow and kFixed) a wave runs at a raised
-    // priority while it issues its loads and at the base priority for its
-    // FP64 flux, so that the waves about to fetch get their requests out
-    // ahead of the ones computing and the memory system stays busy while
-    // others compute: about 5 % of a launch beyond the Infinity Cache, where
-    // the step is bound by HBM, and neutral within it.  With float64 normals
-    // (four more loads per cell) it was 3 % slower, and with 32-bit indices
-    // on a random order 0.8 % slower, so those variants keep the plain
-    // schedule.
-    constexpr bool kPrio = kNarrow && kFixed;
+    // With 16-bit offsets, in the compact layout (kFixed) and beyond the
+    // Infinity Cache (kStream), a wave runs at a raised priority while it
+    // issues its loads and at the base priority for its FP64 flux, so that
+    // the waves about to fetch get their requests out ahead of the ones
+    // computing and the memory system stays busy while others compute:
+    // 4-5 % of a launch beyond the cache, where the step is bound by HBM,
+    // and neutral within it.  Within the cache, with float64 normals (four
+    // more loads per cell) it was 3 % slower, and with 32-bit indices on a
+    // random order 0.8 % slower, so those variants keep the plain schedule.
+    constexpr bool kPrio = kNarrow && (kFixed || kStream);
     if constexpr (kPrio)
         __builtin_amdgcn_s_setprio(1);
     int js[3];
@@ -179,17 +180,17 @@ __device__ __forceinline__ void update_cell(int i, int32_t ld, const double4 *__
         nxs[1] = from_fixed(q.z);
         nys[1] = from_fixed(q.w);
     } else {
-        nxs[0] = nrm[i];
-        nys[0] = nrm[ld + i];
-        nxs[1] = nrm[2 * ld + i];
-        nys[1] = nrm[3 * ld + i];
+        nxs[0] = read_once<kStream>(nrm + i);
+        nys[0] = read_once<kStream>(nrm + ld + i);
+        nxs[1] = read_once<kStream>(nrm + 2 * ld + i);
+        nys[1] = read_once<kStream>(nrm + 3 * ld + i);
     }
     if constexpr (kClosed) {
         nxs[2] = -(nxs[0] + nxs[1]);
         nys[2] = -(nys[0] + nys[1]);
     } else {
-        nxs[2] = nrm[4 * ld + i];
-        nys[2] = nrm[5 * ld + i];
+        nxs[2] = read_once<kStream>(nrm + 4 * ld + i);
+        nys[2] = read_once<kStream>(nrm + 5 * ld + i);
     }
     // The normals enter the flux as opaque values, so every layout runs the
     // same arithmetic: otherwise the compiler folds the derived normal's
@@ -318,9 +319,16 @@ hipError_t launch_step_block(int32_t n, int32_t ld, const double4 *U, double4 *U
     const int tiles = (n + kBlock - 1) / kBlock;
     const int G = (grid <= 0 || grid > tiles) ? tiles : grid;
     fixed = fixed && closed;
-    if (narrow && narrow_interleaved(n, fixed))
+    const bool stream = narrow && narrow_interleaved(n, closed, fixed);
+    if (stream && fixed)
         launch_variant<kBlock, true, true, true, true>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef,
                                                         gamma, s);
+    else if (stream && closed)
+        launch_variant<kBlock, true, true, false, true>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef,
+                                                         gamma, s);
+    else if (stream)
+        launch_variant<kBlock, true, false, false, true>(G, n, ld, U, Un, nb, nb16, nrm, nfx,
+                                                          coef, gamma, s);
     else if (narrow && fixed)
         launch_variant<kBlock, true, true, true>(G, n, ld, U, Un, nb, nb16, nrm, nfx, coef, gamma, s);
     else if (fixed)

@@ -26,9 +26,11 @@ def vortex_case(N: int, perm_seed: int = 2, mesh_seed: int = 1, cfl: float = 0.4
     return m, ic.to_conserved(P), ic.cfl_dt(P, m.area, m.perimeter, cfl)
 
 
-def bumps_case(N: int, perm_seed: int = 2, mesh_seed: int = 1, ic_seed: int = 3, cfl: float = 0.4):
+def bumps_case(N: int, perm_seed: int = 2, mesh_seed: int = 1, ic_seed: int = 3, cfl: float = 0.4,
+               snap_bits: int = 32):
     """Free stream at Mach 0.5 with 32 Gaussian density/pressure bumps."""
-    m = permute_mesh(periodic_mesh(N, seed=mesh_seed), random_permutation(2 * N * N, perm_seed))
+    m = permute_mesh(periodic_mesh(N, seed=mesh_seed, snap_bits=snap_bits),
+                     random_permutation(2 * N * N, perm_seed))
     P = ic.bumps_primitive(m.centroid, seed=ic_seed)
     return m, ic.to_conserved(P), ic.cfl_dt(P, m.area, m.perimeter, cfl)
 

@@ -416,24 +416,27 @@ def test_2048_mesh_beyond_the_cache(torch):
 
 
 @pytest.mark.slow
-def test_streaming_step_equals_cached_step_bitwise(torch):
-    """A mesh whose compact working set (96 B per cell) exceeds the 256 MB
-    Infinity Cache (1200 x 1200 quads, 2,880,000 cells: 276 MB) takes the
-    step variant with non-temporal reads of its per-cell arrays once
-    renumbered, with its 16-bit offsets interleaved with dt/V; on the
-    uploaded (random) order it takes the 32-bit index variant without them.
-    A step gives the same bits in any cell order, so the two runs must agree
-    bit for bit, also after a change of dt (which rewrites the interleaved
-    dt/V)."""
-    log("streaming step 1200")
-    m, U0, dt = bumps_case(1200)
-    assert m.n * 96 > 256 << 20
-    a = fv.Solver(m.nbr, m.nrm, m.area)
-    b = fv.Solver(m.nbr, m.nrm, m.area)
+@pytest.mark.parametrize("layout,bytes_per_update", [("compact", 96), ("float64 normals", 112),
+                                                      ("open normals", 128)])
+def test_streaming_step_equals_cached_step_bitwise(torch, layout, bytes_per_update):
+    """A renumbered mesh whose working set exceeds the 256 MB Infinity Cache
+    (1200 x 1200 quads, 2,880,000 cells: 276 MB in the compact layout, 322
+    MB with float64 normals, 369 MB with all three normals stored) takes the
+    step variant with non-temporal reads of its per-cell arrays and its
+    16-bit offsets interleaved with dt/V; on the uploaded (random) order it
+    takes the 32-bit index variant without them.  A step gives the same bits
+    in any cell order, so the two runs must agree bit for bit, also after a
+    change of dt (which rewrites the interleaved dt/V)."""
+    log(f"streaming step 1200, {layout}")
+    m, U0, dt = bumps_case(1200, snap_bits=40 if layout == "float64 normals" else 32)
+    nrm = open_normals(m) if layout == "open normals" else m.nrm
+    assert m.n * bytes_per_update > 256 << 20
+    a = fv.Solver(m.nbr, nrm, m.area)
+    b = fv.Solver(m.nbr, nrm, m.area)
     try:
         a.upload_state(U0)
         a.renumber(fv.FV_ORDER_CM)
-        assert a.bytes_per_update() == 96
+        assert a.bytes_per_update() == bytes_per_update
         a.step(5, dt)
         a.step(3, 0.5 * dt)
         got = a.download()
