@@ -589,9 +589,11 @@ def main() -> int:
 
     hbm = None
     general = None
+    general_hbm = None
     if args.hbm_N > 0:
         hbm = hbm_resident_step(dev, args.hbm_N, 200, warm_steps=200)
         general = hbm_resident_step(dev, N, 400, snap_bits=40, warm_steps=800)
+        general_hbm = hbm_resident_step(dev, args.hbm_N, 200, snap_bits=40, warm_steps=200)
         torch.cuda.empty_cache()
     batch = None
     if not args.skip_batch:
@@ -649,6 +651,8 @@ def main() -> int:
         # the same kernel on the same mesh snapped to a finer grid, so that
         # the two stored normals stay float64 (the general-mesh layout)
         "general_layout": general,
+        # ... and on the mesh beyond the Infinity Cache
+        "general_layout_hbm_resident": general_hbm,
         # the 64-mesh batch (20k..500k cells each, 11.9M in all), 500 steps
         "batch": batch,
         "cpu_baseline": cpu,
