@@ -18,10 +18,12 @@
 # the 2,097,152-cell workload, for the renumbering kernels and the step.
 # Output rprof_*.  Summarise with python profile_summary.py renumber.
 #
-# `profile.sh hbm`: the step alone on the 2048 x 2048-quad mesh (8,388,608
-# cells, working set beyond the Infinity Cache; bench.py --workload hbm): a
-# kernel trace, then FETCH_SIZE and WRITE_SIZE with the calibration copy.
-# Output hprof_*.  Summarise with python profile_summary.py hbm.
+# `profile.sh hbm [32|40]`: the step alone on the 2048 x 2048-quad mesh
+# (8,388,608 cells, working set beyond the Infinity Cache; bench.py
+# --workload hbm, coordinates on a 2^-32 grid, or 2^-40 for float64
+# normals): a kernel trace, then FETCH_SIZE and WRITE_SIZE with the
+# calibration copy.  Output hprof_*.  Summarise with python
+# profile_summary.py hbm.
 #
 # `profile.sh orders`: the random / AM1 / Cuthill-McKee comparison on the
 # 512 x 512-quad irregular mesh (tests/test_gpu_irregular.py) under the L2
@@ -49,7 +51,9 @@ if [ "${1:-}" = "renumber" ]; then
     exit 0
 fi
 if [ "${1:-}" = "hbm" ]; then
-    HBM=(python3 "$ROOT/bench.py" --workload hbm --hbm-N 2048)
+    # optional second argument: the coordinate grid (32: compact normals,
+    # 40: float64 normals)
+    HBM=(python3 "$ROOT/bench.py" --workload hbm --hbm-N 2048 --snap-bits "${2:-32}")
     echo "[profile] hbm: kernel trace" >&2
     timeout -k 10 300 rocprofv3 --kernel-trace --stats -f csv -d "$OUT/hprof_trace" -o trace -- \
         "${HBM[@]}" --fv-steps 200 > "$OUT/hprof_trace.log" 2>&1

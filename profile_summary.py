@@ -132,12 +132,14 @@ def main_hbm() -> int:
     """profile.sh hbm: the step on the 2048 x 2048-quad mesh."""
     cells = 2 * 2048 * 2048
     lines = trace_table("hprof")
+    table, step, _ = byte_table("hprof", cells)
     # the step's launches in order: the warm-up ones, then the timed ones
     path = os.path.join(OUT, "hprof_trace", "trace_kernel_trace.csv")
     rows = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
                   for r in csv.DictReader(open(path)) if "fv_step_kernel" in r["Kernel_Name"])
     us = [(e - b) / 1e3 for b, e in rows]
-    if len(us) >= 40:
+    if len(us) >= 40 and step:
+        moved = step[0] + step[1]
         lines.append("")
         lines.append("fv_step_kernel launches in order, mean us per block of 20: "
                      + ", ".join(f"{st.mean(us[i:i + 20]):.1f}" for i in range(0, len(us), 20)))
@@ -145,9 +147,9 @@ def main_hbm() -> int:
         lines.append("")
         lines.append(f"fv_step_kernel: first {half} launches {st.mean(us[:half]):.2f} us, "
                      f"last {len(us) - half} launches {st.mean(us[half:]):.2f} us "
-                     f"({cells * 96 / st.mean(us[half:]) / 1e3:.0f} GB/s at 96 B per cell)")
+                     f"({moved / st.mean(us[half:]) / 1e3:.0f} GB/s at the measured "
+                     f"{moved / cells:.1f} B per cell)")
     lines.append("")
-    table, step, _ = byte_table("hprof", cells)
     lines += table
     for name in ("hprof_trace.log", "hprof_fetch.log"):
         log = os.path.join(OUT, name)
